@@ -1,0 +1,105 @@
+"""The five benchmark workloads as plain geometry dictionaries.
+
+Keys (all SI units: metres, seconds, m/s, Hz):
+  nz, nx, dz, dx   physical grid (z down, slow index; x fast index); point (i, j)
+                   sits at z = i*dz, x = j*dx, origin at the top-left corner.
+  nbl              absorbing-layer thickness in grid points on every side.
+  f0, tmax         Ricker peak frequency and record length.
+  dt_frac, vmax    the time step is dt_frac times the leapfrog stability limit
+                   at velocity vmax (both sides compute that limit themselves).
+  src, rec         [n][2] (z, x) positions of shots and receivers.
+  ncz, ncx         regular control-node grid (corners included).
+  node_lo, node_hi [ncz*ncx] search box per node (row-major, z-major).
+  damp_R           target reflection coefficient of the absorbing layer.
+  model            recipe of the true model (generator name and seed).
+  particles, particle_seed   swarm size and seed of the initial draw.
+
+Config 2 is a list of three such dictionaries (three grid sizes in one batch).
+"""
+import numpy as np
+
+from .models import two_layer, layered_faulted
+
+CONFIG_NAMES = ("tiny", "realistic", "batched", "surrogate", "full")
+
+
+def _prior_box(nz, dz, ncz, ncx, v0=1500.0, v1=5500.0, lo_min=1400.0, hi_max=6000.0):
+    """Search box centred on a 1-D prior increasing linearly with depth.
+
+    Node row a sits at depth a*(nz-1)*dz/(ncz-1); its box is
+    [max(lo_min, 0.7*v_prior), min(hi_max, 1.3*v_prior)].
+    """
+    zrow = np.arange(ncz) * (nz - 1) * dz / (ncz - 1)
+    vprior = v0 + (v1 - v0) * zrow / ((nz - 1) * dz)
+    lo = np.maximum(lo_min, 0.7 * vprior)
+    hi = np.minimum(hi_max, 1.3 * vprior)
+    return np.repeat(lo, ncx), np.repeat(hi, ncx)
+
+
+def _surface_line(n, spacing):
+    return [[0.0, k * spacing] for k in range(n)]
+
+
+def _shots_even(nshots, nx, dx):
+    """nshots sources on the surface at x = (s+1)*L/(nshots+1), snapped to the grid."""
+    L = (nx - 1) * dx
+    return [[0.0, round((s + 1) * L / (nshots + 1) / dx) * dx] for s in range(nshots)]
+
+
+def _layered_geometry(nz, nx, h, nshots, rec_step, f0, tmax, ncz, ncx, seed, pseed, npart):
+    lo, hi = _prior_box(nz, h, ncz, ncx)
+    nrec = (nx - 1) * h // rec_step + 1
+    return {
+        "nz": nz, "nx": nx, "dz": float(h), "dx": float(h), "nbl": 40,
+        "f0": float(f0), "tmax": float(tmax), "dt_frac": 0.4, "vmax": 6000.0,
+        "src": _shots_even(nshots, nx, float(h)),
+        "rec": _surface_line(int(nrec), float(rec_step)),
+        "ncz": ncz, "ncx": ncx, "node_lo": lo, "node_hi": hi,
+        "damp_R": 1e-3,
+        "model": {"kind": "layered_faulted", "seed": seed},
+        "particles": npart, "particle_seed": pseed,
+    }
+
+
+def config(name):
+    """Return the geometry dictionary (or list of them) of a named workload."""
+    if name in ("tiny", 0):
+        nz = nx = 101
+        return {
+            "nz": nz, "nx": nx, "dz": 10.0, "dx": 10.0, "nbl": 40,
+            "f0": 10.0, "tmax": 1.0, "dt_frac": 0.4, "vmax": 2700.0,
+            "src": [[0.0, 500.0]],
+            "rec": _surface_line(101, 10.0),
+            "ncz": 2, "ncx": 3,
+            "node_lo": np.full(6, 1400.0), "node_hi": np.full(6, 2700.0),
+            "damp_R": 1e-3,
+            "model": {"kind": "two_layer", "seed": 1, "v_top": 1500.0, "v_bottom": 2500.0},
+            "particles": 8, "particle_seed": 2,
+        }
+    if name in ("realistic", 1, "surrogate", 3):
+        g = _layered_geometry(301, 921, 10, 16, 20, 5.0, 3.0, 5, 12, seed=3, pseed=4, npart=32)
+        if name in ("surrogate", 3):
+            g["particles"] = 64
+            g["candidates_per_particle"] = 16
+        return g
+    if name in ("batched", 2):
+        out = []
+        for (nz, nx), seed in zip(((201, 601), (301, 921), (401, 1201)), (5, 6, 7)):
+            out.append(_layered_geometry(nz, nx, 10, 16, 20, 5.0, 3.0, 5, 12,
+                                         seed=seed, pseed=10, npart=64))
+        return out
+    if name in ("full", 4):
+        return _layered_geometry(601, 1841, 5, 32, 10, 6.0, 4.0, 8, 20, seed=8, pseed=9, npart=128)
+    raise KeyError(name)
+
+
+def true_model(geom):
+    """Generate the seeded true velocity model vp[nz][nx] (float64) of a geometry."""
+    m = geom["model"]
+    if m["kind"] == "two_layer":
+        vp, _ = two_layer(geom["nz"], geom["nx"], geom["dz"], geom["dx"],
+                          m["v_top"], m["v_bottom"], m["seed"])
+        return vp
+    if m["kind"] == "layered_faulted":
+        return layered_faulted(geom["nz"], geom["nx"], geom["dz"], geom["dx"], m["seed"])
+    raise KeyError(m["kind"])
