@@ -1,0 +1,190 @@
+/*
+ * empso.h - C ABI of the MI355X (gfx950) fitness-evaluation library.
+ *
+ * The library computes the fitness of velocity-model candidates for the
+ * elitist-mutated particle swarm search of Mojica and Kukreja (arXiv
+ * 1905.12795). The problem it solves is the one the paper states in its
+ * Testing approach section: minimise, over control-node velocities x inside a
+ * search box,
+ *
+ *     phi(x) = 1/2 sum_s || R u_s(B x) - d_s^obs ||^2
+ *
+ * where B is the bilinear two-grid map from control nodes to the FD grid,
+ * u_s is the 2-D constant-density acoustic wavefield of shot s (finite
+ * differences, second order in time, eighth order in space, damping absorbing
+ * layer, Ricker source), R samples it at the receivers at every time step,
+ * and the l2 misfit is summed over shots (Results section: a particle's
+ * fitness needs all of its shots).
+ *
+ * Conventions (identical in every entry point):
+ *   - Grid point (i, j) of the physical grid is at z = i*dz, x = j*dx; z points
+ *     down; the origin is the top-left corner. The padded grid adds nbl points
+ *     of absorbing layer on every side; beyond it the field is zero.
+ *   - Scheme, with m = 1/v^2, damping d and a = d*dt/2:
+ *       u^{n+1} = u^n + delta^{n+1},
+ *       delta^{n+1} = [ (1-a) delta^n + (v dt)^2 (Lap_h u^n + f^n) ] / (1+a),
+ *     which is the centred scheme u^{n+1} = [2u^n - (1-a)u^{n-1} + (v dt)^2
+ *     (Lap_h u^n + f^n)]/(1+a) carried in increment form for FP32 accuracy.
+ *     Lap_h uses the eighth-order central weights (-205/72, 8/5, -1/5, 8/315,
+ *     -1/560). u^0 = u^{-1} = 0.
+ *   - Damping: d = d0 (l/nbl)^2 per axis, d0 = 3 vmax ln(1/R)/(2 nbl h), with l
+ *     the depth into the layer in points; the z and x parts add.
+ *   - Source: f^n = w(n dt)/(dz dx) at the source point, entering the step
+ *     n -> n+1; w is a Ricker wavelet of peak frequency f0 delayed by 1/f0.
+ *   - Traces: d[n][r] = u^n at receiver r, n = 0 .. nt-1 (every time step).
+ *   - Misfit: 1/2 sum of squared residuals over time samples and receivers.
+ *   - Sources and receivers must lie on grid points; all receivers of a
+ *     problem share one grid row and occupy distinct columns (ENOTSUP
+ *     otherwise).
+ *
+ * Memory: every device array (fields, traces, observed data, fitness,
+ * workspace) is owned by the caller. Problem handles are owned by the library
+ * and hold small device tables (wavelet, damping, receiver maps); they are
+ * immutable after creation and may be shared between streams.
+ *
+ * Streams: entry points that take an empso_stream enqueue work on that HIP
+ * stream (a hipStream_t; NULL means the default stream) and return; results
+ * are valid once the stream has reached that point. Calls that overlap on
+ * different streams must use different workspaces.
+ *
+ * Errors: every entry point returns EMPSO_OK (0) or a negative status. All
+ * validation happens before anything is enqueued: on error nothing has been
+ * enqueued and output arrays are untouched. empso_last_error() returns a
+ * thread-local message describing the last failure.
+ */
+#ifndef EMPSO_H
+#define EMPSO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EMPSO_OK          0
+#define EMPSO_EINVAL     (-1)  /* null pointer, non-positive size, bad geometry          */
+#define EMPSO_ECFL       (-2)  /* dt above the leapfrog stability limit at vmax          */
+#define EMPSO_ERANGE     (-3)  /* a velocity outside [vmin, vmax] or not finite          */
+#define EMPSO_EWORKSPACE (-4)  /* workspace too small                                     */
+#define EMPSO_EHIP       (-5)  /* a HIP runtime call failed (see empso_last_error)        */
+#define EMPSO_ENOTSUP    (-6)  /* valid request outside what this library implements      */
+
+typedef void *empso_stream;                 /* hipStream_t */
+typedef struct empso_problem empso_problem; /* opaque, immutable after creation */
+
+/* One modelling problem: grid, time axis, acquisition, control-node grid.
+ * All values on the host, SI units (m, s, m/s, Hz). Arrays are read during
+ * empso_problem_create only. */
+typedef struct {
+    int32_t nz, nx;          /* physical grid points (z slow, x fast)                  */
+    double dz, dx;           /* grid spacing                                            */
+    int32_t nbl;             /* absorbing-layer points on every side (paper: nbpml)     */
+    double dt;               /* time step; must satisfy dt <= stable limit at vmax      */
+    int32_t nt;              /* time samples, t = 0 included                            */
+    double f0;               /* Ricker peak frequency                                   */
+    int32_t nshots;          /* number of shots                                         */
+    const double *src_zx;    /* [nshots][2] source (z, x) positions                     */
+    int32_t nrec;            /* receivers per shot (same spread for every shot)         */
+    const double *rec_zx;    /* [nrec][2] receiver (z, x) positions                     */
+    int32_t ncz, ncx;        /* regular control-node grid, corners included, >= 2 each  */
+    double vmin, vmax;       /* hard velocity bounds; dt is checked against vmax        */
+    double damp_R;           /* target reflection coefficient of the layer (e.g. 1e-3)  */
+} empso_geometry;
+
+/* Read-only facts about a problem (for sizing caller-owned arrays). */
+typedef struct {
+    int32_t nz, nx, nbl, nt, nshots, nrec, ncz, ncx;
+    int32_t Nz, Nx;          /* padded grid: nz + 2 nbl, nx + 2 nbl                    */
+    int32_t row_stride;      /* floats per stored row of an internal field              */
+    int64_t updates_per_run; /* Nz * Nx * (nt - 1): point updates of one shot           */
+} empso_problem_info;
+
+/* Tuning of the finite-difference kernels (chosen by empso_autotune). */
+typedef struct {
+    int32_t variant;         /* kernel family: 0 = single-step z-march                  */
+    int32_t bz;              /* rows per tile                                            */
+    int32_t tsteps;          /* time steps per launch (temporal-blocking depth)         */
+    int32_t use_graph;       /* 1: replay the time loop from a captured HIP graph       */
+} empso_tuning;
+
+/* Status name ("EMPSO_OK", ...). Never NULL. */
+const char *empso_status_string(int status);
+
+/* Thread-local description of the last error on this thread. Never NULL. */
+const char *empso_last_error(void);
+
+/* Largest stable time step of the scheme at velocity vmax (von Neumann limit
+ * of the leapfrog with the eighth-order stencil):
+ *   dt_stab = 2 / (vmax sqrt((2048/315) (1/dz^2 + 1/dx^2))).
+ * Testing approach section: second order in time, eighth order in space. */
+int empso_stable_dt(double vmax, double dz, double dx, double *dt_out);
+
+/* Create a problem. Validates the geometry (EINVAL, ECFL, ENOTSUP), builds the
+ * wavelet, damping and receiver tables and uploads them to the current
+ * device. *out receives the handle (NULL on error). */
+int empso_problem_create(const empso_geometry *geom, empso_problem **out);
+
+/* Destroy a problem created by empso_problem_create (NULL is ignored). The
+ * caller must make sure no enqueued work still uses it. */
+void empso_problem_destroy(empso_problem *prob);
+
+int empso_problem_get_info(const empso_problem *prob, empso_problem_info *info);
+
+/* Bilinear two-grid interpolation (Testing approach section): control-node
+ * velocities nodes_d[nmodels][ncz*ncx] (device, FP32, row-major z-major)
+ * become vp_d[nmodels][nz][nx] (device, FP32). Node (a, b) sits at grid point
+ * (a (nz-1)/(ncz-1), b (nx-1)/(ncx-1)). */
+int empso_vp_from_nodes(const empso_problem *prob, int32_t nmodels, const float *nodes_d,
+                        float *vp_d, empso_stream stream);
+
+/* Workspace bytes for empso_forward_shots with nsh shots. */
+size_t empso_forward_workspace_bytes(const empso_problem *prob, int32_t nsh);
+
+/* Model shots shot0 .. shot0+nsh-1 in the physical-grid model vp_d[nz][nx]
+ * (device, FP32; copied once to the host for the range check, so this call
+ * waits for the stream) and write traces_d[nsh][nt][nrec] (device, FP32).
+ * The model is extended into the absorbing layer by nearest-value copy.
+ * ERANGE if a velocity lies outside [vmin, vmax]. */
+int empso_forward_shots(const empso_problem *prob, const float *vp_d, int32_t shot0, int32_t nsh,
+                        float *traces_d, void *ws, size_t ws_bytes, empso_stream stream);
+
+/* Workspace bytes for empso_misfit over n elements. */
+size_t empso_misfit_workspace_bytes(int64_t n);
+
+/* out_d[0] = 1/2 sum_k (a_d[k] - b_d[k])^2 over n elements (device, FP32
+ * inputs, FP64 accumulation in a fixed order, FP32 result). Deterministic. */
+int empso_misfit(const float *a_d, const float *b_d, int64_t n, float *out_d,
+                 void *ws, size_t ws_bytes, empso_stream stream);
+
+/* Workspace bytes for empso_fitness_batch over np particles; particle p uses
+ * problem probs[prob_of_particle[p]] (host array). */
+size_t empso_fitness_workspace_bytes(const empso_problem *const *probs, int32_t nprob,
+                                     const int32_t *prob_of_particle, int32_t np);
+
+/* Fitness of np particles (Results section: a particle's fitness is the sum
+ * over all shots of its problem of the l2 misfit). All shots of all particles
+ * advance together, one launch per time step or per block of time steps.
+ *   probs[nprob]              problems (grids may differ; all must share nt)
+ *   obs_d[nprob]              per problem, device FP32 [nshots][nt][nrec]
+ *   prob_of_particle[np]      host, problem index of each particle
+ *   nodes_h[np][ld_nodes]     host FP64 control-node velocities (ld_nodes >=
+ *                             the largest ncz*ncx); range-checked on the host:
+ *                             ERANGE if outside [vmin, vmax] or not finite
+ *   fitness_d[np]             device FP32 output; +inf if the wavefield of
+ *                             some shot became non-finite
+ * tuning may be NULL (library default). */
+int empso_fitness_batch(const empso_problem *const *probs, int32_t nprob,
+                        const float *const *obs_d, const int32_t *prob_of_particle, int32_t np,
+                        const double *nodes_h, int32_t ld_nodes, float *fitness_d,
+                        void *ws, size_t ws_bytes, const empso_tuning *tuning,
+                        empso_stream stream);
+
+/* Default tuning used when NULL is passed. */
+int empso_default_tuning(empso_tuning *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EMPSO_H */

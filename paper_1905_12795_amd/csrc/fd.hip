@@ -1,0 +1,1003 @@
+// Finite-difference fitness evaluation for gfx950 (MI355X).
+//
+// Paper: Mojica and Kukreja, arXiv 1905.12795, Testing approach section. The
+// fitness of a particle is the l2 misfit between observed traces and traces
+// modelled with a 2-D constant-density acoustic finite-difference scheme
+// (second order in time, eighth order in space, damping absorbing layer,
+// Ricker source, one receiver per surface grid column), summed over shots;
+// control-node velocities reach the FD grid by bilinear interpolation.
+//
+// Layout in HBM (per run = one particle x one shot):
+//   three FP32 fields u_even, u_odd, delta, each (Nz + 8) rows x S floats,
+//   x fastest. Row s holds padded row I = s - 4 and column c holds padded
+//   column J = c - 4; the 4-deep ring around the padded grid and the row tail
+//   up to the stride S (a multiple of 64 floats, S >= Nx + 8) stay zero, so
+//   the stencil needs no bounds tests. The coefficient field C = (v dt)^2 of a
+//   particle uses the same layout and is shared by all of its shots.
+// Step n -> n+1 reads u^n from the buffer of parity n and writes u^{n+1} to
+// the other one; delta is updated in place.
+//
+// Kernel shape: one 64-lane wavefront owns a tile of 256 columns (4 adjacent
+// columns per lane, 16-byte loads) by bz rows and marches down the rows,
+// keeping the 9 rows of its z-stencil in registers; x-neighbours come from the
+// adjacent lanes by cross-lane permutes, the two tile-edge lanes fetch the
+// 4-column halos. Damping, source injection and receiver residuals are fused
+// into the same pass. Tiles are ordered particle, z-strip, x-strip, shot
+// (shot fastest) so that the shots of a particle read the shared coefficient
+// tile back to back from L2, and block indices are remapped so that
+// consecutive tiles run on the same XCD.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <unordered_map>
+#include <vector>
+
+#include "common.h"
+
+namespace empso {
+
+// ---------------------------------------------------------------------------
+// Error state
+// ---------------------------------------------------------------------------
+static thread_local std::string g_err;
+
+void set_error(const char *fmt, ...) {
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+}
+void clear_error() { g_err.clear(); }
+
+// Eighth-order central weights of the second derivative (Fornberg 1988).
+static const double kW[5] = {-205.0 / 72.0, 8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0};
+// |symbol| at the Nyquist wavenumber: |w0 + 2 sum_k w_k (-1)^k| = 2048/315.
+static const double kSymbolMax = 2048.0 / 315.0;
+
+static const int kHalo = 4;        // zero ring around the padded grid
+static const int kLanesX = 64;     // lanes per wavefront
+static const int kColsPerLane = 4;
+static const int kTileX = kLanesX * kColsPerLane;
+
+}  // namespace empso
+
+using namespace empso;
+
+// ---------------------------------------------------------------------------
+// Problem
+// ---------------------------------------------------------------------------
+struct empso_problem {
+    empso_geometry g;
+    int Nz, Nx, S;             // padded sizes, stored row stride (floats)
+    int D;                     // ncz * ncx
+    std::vector<int> srcI, srcJ;   // padded indices per shot
+    int recI;                  // padded receiver row
+    std::vector<int> reccol;   // padded column of each receiver
+    float *d_wav = nullptr;    // [nt]
+    float *d_az = nullptr;     // [Nz] a = d dt / 2 along z
+    float *d_ax = nullptr;     // [Nx]
+    int *d_recmap = nullptr;   // [Nx] receiver index of a padded column or -1
+    int *d_reccol = nullptr;   // [nrec]
+    float c0, cz[4], cx[4], wscale;
+};
+
+extern "C" const char *empso_status_string(int s) {
+    switch (s) {
+        case EMPSO_OK: return "EMPSO_OK";
+        case EMPSO_EINVAL: return "EMPSO_EINVAL";
+        case EMPSO_ECFL: return "EMPSO_ECFL";
+        case EMPSO_ERANGE: return "EMPSO_ERANGE";
+        case EMPSO_EWORKSPACE: return "EMPSO_EWORKSPACE";
+        case EMPSO_EHIP: return "EMPSO_EHIP";
+        case EMPSO_ENOTSUP: return "EMPSO_ENOTSUP";
+        default: return "EMPSO_UNKNOWN";
+    }
+}
+
+extern "C" const char *empso_last_error(void) { return g_err.c_str(); }
+
+static double stable_dt_raw(double vmax, double dz, double dx) {
+    return 2.0 / (vmax * std::sqrt(kSymbolMax * (1.0 / (dz * dz) + 1.0 / (dx * dx))));
+}
+
+extern "C" int empso_stable_dt(double vmax, double dz, double dx, double *dt_out) {
+    if (!dt_out) EMPSO_FAIL(EMPSO_EINVAL, "dt_out is NULL");
+    if (!(vmax > 0) || !(dz > 0) || !(dx > 0) || !std::isfinite(vmax) || !std::isfinite(dz) ||
+        !std::isfinite(dx))
+        EMPSO_FAIL(EMPSO_EINVAL, "vmax, dz, dx must be positive and finite");
+    *dt_out = stable_dt_raw(vmax, dz, dx);
+    return EMPSO_OK;
+}
+
+// Grid index of a coordinate that must sit on a grid point (tolerance 1e-6 h).
+static bool on_grid(double pos, double h, int n, int *idx) {
+    double f = pos / h;
+    double r = std::nearbyint(f);
+    if (std::fabs(f - r) > 1e-6) return false;
+    if (r < 0 || r > n - 1) return false;
+    *idx = (int)r;
+    return true;
+}
+
+static void free_problem(empso_problem *p) {
+    if (!p) return;
+    if (p->d_wav) (void)hipFree(p->d_wav);
+    if (p->d_az) (void)hipFree(p->d_az);
+    if (p->d_ax) (void)hipFree(p->d_ax);
+    if (p->d_recmap) (void)hipFree(p->d_recmap);
+    if (p->d_reccol) (void)hipFree(p->d_reccol);
+    delete p;
+}
+
+extern "C" int empso_problem_create(const empso_geometry *gp, empso_problem **out) {
+    clear_error();
+    if (!out) EMPSO_FAIL(EMPSO_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!gp) EMPSO_FAIL(EMPSO_EINVAL, "geometry is NULL");
+    const empso_geometry &g = *gp;
+    if (g.nz < 2 || g.nx < 2 || g.nbl < 0 || g.nt < 1 || g.nshots < 1 || g.nrec < 1)
+        EMPSO_FAIL(EMPSO_EINVAL, "sizes must be positive (nz, nx >= 2, nbl >= 0, nt, nshots, nrec >= 1)");
+    if (g.ncz < 2 || g.ncx < 2) EMPSO_FAIL(EMPSO_EINVAL, "ncz and ncx must be >= 2");
+    if (g.ncz > g.nz || g.ncx > g.nx) EMPSO_FAIL(EMPSO_EINVAL, "more control nodes than grid points");
+    if (!(g.dz > 0) || !(g.dx > 0) || !(g.dt > 0) || !(g.f0 > 0) || !std::isfinite(g.dz) ||
+        !std::isfinite(g.dx) || !std::isfinite(g.dt) || !std::isfinite(g.f0))
+        EMPSO_FAIL(EMPSO_EINVAL, "dz, dx, dt, f0 must be positive and finite");
+    if (!(g.vmin > 0) || !(g.vmax >= g.vmin) || !std::isfinite(g.vmax))
+        EMPSO_FAIL(EMPSO_EINVAL, "need 0 < vmin <= vmax < inf");
+    if (!(g.damp_R > 0 && g.damp_R < 1)) EMPSO_FAIL(EMPSO_EINVAL, "damp_R must lie in (0, 1)");
+    if (!g.src_zx || !g.rec_zx) EMPSO_FAIL(EMPSO_EINVAL, "src_zx / rec_zx is NULL");
+    const int64_t Nz64 = (int64_t)g.nz + 2 * (int64_t)g.nbl, Nx64 = (int64_t)g.nx + 2 * (int64_t)g.nbl;
+    if (Nz64 > (1 << 20) || Nx64 > (1 << 20) || (Nz64 + 8) * (Nx64 + 72) > (int64_t)1 << 31)
+        EMPSO_FAIL(EMPSO_ENOTSUP, "grid too large");
+    if (g.dt > stable_dt_raw(g.vmax, g.dz, g.dx) * (1.0 + 1e-12))
+        EMPSO_FAIL(EMPSO_ECFL, "dt = %g exceeds the stability limit %g at vmax = %g", g.dt,
+                   stable_dt_raw(g.vmax, g.dz, g.dx), g.vmax);
+
+    empso_problem *p = new empso_problem();
+    p->g = g;
+    p->g.src_zx = nullptr;
+    p->g.rec_zx = nullptr;
+    p->Nz = (int)Nz64;
+    p->Nx = (int)Nx64;
+    p->S = (int)align_up((size_t)p->Nx + 2 * kHalo, 64);
+    p->D = g.ncz * g.ncx;
+    for (int s = 0; s < g.nshots; ++s) {
+        int i, j;
+        if (!on_grid(g.src_zx[2 * s], g.dz, g.nz, &i) || !on_grid(g.src_zx[2 * s + 1], g.dx, g.nx, &j)) {
+            free_problem(p);
+            EMPSO_FAIL(EMPSO_ENOTSUP, "source %d is not on a grid point of the physical grid", s);
+        }
+        p->srcI.push_back(i + g.nbl);
+        p->srcJ.push_back(j + g.nbl);
+    }
+    std::vector<int> recmap(p->Nx, -1);
+    p->reccol.resize(g.nrec);
+    for (int r = 0; r < g.nrec; ++r) {
+        int i, j;
+        if (!on_grid(g.rec_zx[2 * r], g.dz, g.nz, &i) || !on_grid(g.rec_zx[2 * r + 1], g.dx, g.nx, &j)) {
+            free_problem(p);
+            EMPSO_FAIL(EMPSO_ENOTSUP, "receiver %d is not on a grid point of the physical grid", r);
+        }
+        if (r == 0) p->recI = i + g.nbl;
+        if (i + g.nbl != p->recI) {
+            free_problem(p);
+            EMPSO_FAIL(EMPSO_ENOTSUP, "receivers must share one grid row");
+        }
+        if (recmap[j + g.nbl] >= 0) {
+            free_problem(p);
+            EMPSO_FAIL(EMPSO_ENOTSUP, "receivers %d and %d share a grid point", recmap[j + g.nbl], r);
+        }
+        recmap[j + g.nbl] = r;
+        p->reccol[r] = j + g.nbl;
+    }
+
+    // Ricker wavelet, peak frequency f0, delay 1/f0 (evaluated in FP64, stored FP32)
+    std::vector<float> wav(g.nt);
+    const double pi = 3.14159265358979323846;
+    for (int n = 0; n < g.nt; ++n) {
+        double tau = n * g.dt - 1.0 / g.f0;
+        double a = pi * pi * g.f0 * g.f0 * tau * tau;
+        wav[n] = (float)((1.0 - 2.0 * a) * std::exp(-a));
+    }
+    // damping a = d dt / 2 with d = d0 (l / nbl)^2 per axis
+    std::vector<float> az(p->Nz, 0.f), ax(p->Nx, 0.f);
+    if (g.nbl > 0) {
+        const double L = std::log(1.0 / g.damp_R);
+        const double d0z = 3.0 * g.vmax * L / (2.0 * g.nbl * g.dz);
+        const double d0x = 3.0 * g.vmax * L / (2.0 * g.nbl * g.dx);
+        for (int I = 0; I < p->Nz; ++I) {
+            int l = std::max(0, std::max(g.nbl - I, I - (p->Nz - 1 - g.nbl)));
+            double r = (double)l / g.nbl;
+            az[I] = (float)(0.5 * g.dt * d0z * r * r);
+        }
+        for (int J = 0; J < p->Nx; ++J) {
+            int l = std::max(0, std::max(g.nbl - J, J - (p->Nx - 1 - g.nbl)));
+            double r = (double)l / g.nbl;
+            ax[J] = (float)(0.5 * g.dt * d0x * r * r);
+        }
+    }
+    const double idz2 = 1.0 / (g.dz * g.dz), idx2 = 1.0 / (g.dx * g.dx);
+    p->c0 = (float)(kW[0] * (idz2 + idx2));
+    for (int k = 0; k < 4; ++k) {
+        p->cz[k] = (float)(kW[k + 1] * idz2);
+        p->cx[k] = (float)(kW[k + 1] * idx2);
+    }
+    p->wscale = (float)(1.0 / (g.dz * g.dx));
+
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = hipMalloc(&p->d_wav, sizeof(float) * g.nt);
+    if (e == hipSuccess) e = hipMalloc(&p->d_az, sizeof(float) * p->Nz);
+    if (e == hipSuccess) e = hipMalloc(&p->d_ax, sizeof(float) * p->Nx);
+    if (e == hipSuccess) e = hipMalloc(&p->d_recmap, sizeof(int) * p->Nx);
+    if (e == hipSuccess) e = hipMalloc(&p->d_reccol, sizeof(int) * g.nrec);
+    if (e == hipSuccess) e = hipMemcpy(p->d_wav, wav.data(), sizeof(float) * g.nt, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p->d_az, az.data(), sizeof(float) * p->Nz, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p->d_ax, ax.data(), sizeof(float) * p->Nx, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p->d_recmap, recmap.data(), sizeof(int) * p->Nx, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(p->d_reccol, p->reccol.data(), sizeof(int) * g.nrec, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        free_problem(p);
+        EMPSO_FAIL(EMPSO_EHIP, "device table upload failed: %s", hipGetErrorString(e));
+    }
+    *out = p;
+    return EMPSO_OK;
+}
+
+extern "C" void empso_problem_destroy(empso_problem *p) { free_problem(p); }
+
+extern "C" int empso_problem_get_info(const empso_problem *p, empso_problem_info *info) {
+    if (!p || !info) EMPSO_FAIL(EMPSO_EINVAL, "NULL argument");
+    info->nz = p->g.nz;
+    info->nx = p->g.nx;
+    info->nbl = p->g.nbl;
+    info->nt = p->g.nt;
+    info->nshots = p->g.nshots;
+    info->nrec = p->g.nrec;
+    info->ncz = p->g.ncz;
+    info->ncx = p->g.ncx;
+    info->Nz = p->Nz;
+    info->Nx = p->Nx;
+    info->row_stride = p->S;
+    info->updates_per_run = (int64_t)p->Nz * p->Nx * (int64_t)(p->g.nt > 0 ? p->g.nt - 1 : 0);
+    return EMPSO_OK;
+}
+
+extern "C" int empso_default_tuning(empso_tuning *t) {
+    if (!t) EMPSO_FAIL(EMPSO_EINVAL, "NULL argument");
+    t->variant = 0;
+    t->bz = 36;
+    t->tsteps = 1;
+    t->use_graph = 1;
+    return EMPSO_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Device-side descriptors
+// ---------------------------------------------------------------------------
+struct RunDesc {
+    float *u0, *u1, *dl;        // fields (storage base, ring included)
+    const float *C;             // coefficient field of the particle
+    const float *obs;           // [nt][nrec] observed traces of this shot (fitness mode)
+    float *traces;              // [nt][nrec] output (record mode) or NULL
+    double *acc;                // [nrec] running sum of squared residuals
+    const float *wav, *az, *ax;
+    const int *recmap, *reccol;
+    int Nz, Nx, S, nrec, recS, srcS, srcC, nt;
+    float c0, cz1, cz2, cz3, cz4, cx1, cx2, cx3, cx4, wscale;
+};
+
+struct CoefDesc {
+    float *C;                   // output coefficient field
+    const float *nodes;         // [ncz*ncx] (node mode) or NULL
+    const float *vp;            // [nz][nx] (model mode) or NULL
+    int nz, nx, nbl, ncz, ncx, Nz, Nx, S;
+    float dt;
+};
+
+// ---------------------------------------------------------------------------
+// Kernels
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float4 ld4(const float *p) { return *reinterpret_cast<const float4 *>(p); }
+__device__ __forceinline__ void st4(float *p, float4 v) { *reinterpret_cast<float4 *>(p) = v; }
+
+// Bilinear interpolation of a regular node grid at physical grid point (i, j).
+// Cell indices come from exact integer division so that node rows/columns that
+// fall on grid points are reproduced exactly.
+__device__ __forceinline__ float bilinear_at(const float *nd, int ncz, int ncx, int nz, int nx, int i, int j) {
+    int ni = i * (ncz - 1), a = ni / (nz - 1);
+    float t = (float)(ni - a * (nz - 1)) / (float)(nz - 1);
+    if (a >= ncz - 1) { a = ncz - 2; t = 1.0f; }
+    int nj = j * (ncx - 1), b = nj / (nx - 1);
+    float u = (float)(nj - b * (nx - 1)) / (float)(nx - 1);
+    if (b >= ncx - 1) { b = ncx - 2; u = 1.0f; }
+    const float v00 = nd[a * ncx + b], v01 = nd[a * ncx + b + 1];
+    const float v10 = nd[(a + 1) * ncx + b], v11 = nd[(a + 1) * ncx + b + 1];
+    return (1.0f - t) * (1.0f - u) * v00 + (1.0f - t) * u * v01 + t * (1.0f - u) * v10 + t * u * v11;
+}
+
+__global__ void k_vp_from_nodes(const float *__restrict__ nodes, float *__restrict__ vp, int ncz, int ncx,
+                                int nz, int nx) {
+    const int m = blockIdx.y;
+    const float *nd = nodes + (size_t)m * ncz * ncx;
+    const int64_t npts = (int64_t)nz * nx;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < npts; k += (int64_t)gridDim.x * blockDim.x) {
+        int i = (int)(k / nx), j = (int)(k - (int64_t)i * nx);
+        vp[(size_t)m * npts + k] = bilinear_at(nd, ncz, ncx, nz, nx, i, j);
+    }
+}
+
+// Coefficient field C = (v dt)^2 on the stored layout (zero outside the padded grid).
+__global__ void k_coef(const CoefDesc *__restrict__ cds) {
+    const CoefDesc cd = cds[blockIdx.y];
+    const int rows = cd.Nz + 2 * kHalo;
+    const int64_t npts = (int64_t)rows * cd.S;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < npts; k += (int64_t)gridDim.x * blockDim.x) {
+        const int s = (int)(k / cd.S), c = (int)(k - (int64_t)s * cd.S);
+        const int I = s - kHalo, J = c - kHalo;
+        float val = 0.0f;
+        if (I >= 0 && I < cd.Nz && J >= 0 && J < cd.Nx) {
+            const int i = min(max(I - cd.nbl, 0), cd.nz - 1);
+            const int j = min(max(J - cd.nbl, 0), cd.nx - 1);
+            const float v = cd.nodes ? bilinear_at(cd.nodes, cd.ncz, cd.ncx, cd.nz, cd.nx, i, j)
+                                     : cd.vp[(size_t)i * cd.nx + j];
+            const float vd = v * cd.dt;
+            val = vd * vd;
+        }
+        cd.C[k] = val;
+    }
+}
+
+__global__ void k_zero(float4 *__restrict__ p, int64_t n4) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n4; k += (int64_t)gridDim.x * blockDim.x)
+        p[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+// Blocks are dispatched round-robin over the 8 XCDs (block b -> XCD b % 8).
+// Give each XCD a contiguous range of logical blocks so that neighbouring
+// tiles share an L2. The grid is padded to a multiple of 8.
+__device__ __forceinline__ int xcd_logical_block(int b, int nblocks) {
+    const int per = nblocks >> 3;
+    return (b & 7) * per + (b >> 3);
+}
+
+__device__ __forceinline__ void sample_receivers(const RunDesc &R, int n, int J0, const float4 ce) {
+    const float u4[4] = {ce.x, ce.y, ce.z, ce.w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int J = J0 + k;
+        if (J < R.Nx) {
+            const int r = R.recmap[J];
+            if (r >= 0) {
+                const size_t o = (size_t)n * R.nrec + r;
+                if (R.traces) {
+                    R.traces[o] = u4[k];
+                } else {
+                    const float res = u4[k] - R.obs[o];
+                    R.acc[r] += (double)res * (double)res;
+                }
+            }
+        }
+    }
+}
+
+// One time step n -> n+1 for every tile. Each wavefront owns one tile.
+template <int BZ>
+__global__ __launch_bounds__(256) void k_step(const RunDesc *__restrict__ runs, const int4 *__restrict__ tiles,
+                                              int ntiles, int n) {
+    const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
+    const int tix = __builtin_amdgcn_readfirstlane(lb * 4 + (int)(threadIdx.x >> 6));
+    if (tix >= ntiles) return;
+    const int lane = threadIdx.x & 63;
+    const int4 t = tiles[tix];
+    const RunDesc &R = runs[t.x];
+    const int S = R.S;
+    const float *__restrict__ uin = (n & 1) ? R.u1 : R.u0;
+    float *__restrict__ uout = (n & 1) ? R.u0 : R.u1;
+    float *__restrict__ dl = R.dl;
+    const float *__restrict__ Cf = R.C;
+    const int c = t.z + 4 * lane;          // stored column of this lane's first element
+    const bool live = c < S;                // inside the stored row
+    const bool store = c < R.Nx + kHalo;    // holds at least one grid column
+    const int J0 = c - kHalo;
+    const int s0 = t.y;
+    const int s1 = min(s0 + BZ, R.Nz + kHalo);
+
+    float axk[4];
+    bool xdamp = false;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        axk[k] = (J0 + k < R.Nx) ? R.ax[J0 + k] : 0.0f;
+        xdamp |= axk[k] != 0.0f;
+    }
+    const bool tile_xdamp = __any(xdamp);
+    const float c0 = R.c0, cz1 = R.cz1, cz2 = R.cz2, cz3 = R.cz3, cz4 = R.cz4;
+    const float cx1 = R.cx1, cx2 = R.cx2, cx3 = R.cx3, cx4 = R.cx4;
+    const float fsrc = R.wav[n] * R.wscale;
+    const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+
+    float4 q[9];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) q[j] = live ? ld4(uin + (size_t)(s0 - 4 + j) * S + c) : z4;
+
+    for (int sb = s0; sb < s1; sb += 9) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            const int s = sb + k;
+            if (s < s1) {
+                q[(k + 8) % 9] = live ? ld4(uin + (size_t)(s + 4) * S + c) : z4;
+                const float4 ce = q[(k + 4) % 9];
+                const float4 p1 = q[(k + 3) % 9], m1 = q[(k + 5) % 9];
+                const float4 p2 = q[(k + 2) % 9], m2 = q[(k + 6) % 9];
+                const float4 p3 = q[(k + 1) % 9], m3 = q[(k + 7) % 9];
+                const float4 p4 = q[(k + 0) % 9], m4 = q[(k + 8) % 9];
+                float4 lf, rt;
+                lf.x = __shfl_up(ce.x, 1); lf.y = __shfl_up(ce.y, 1);
+                lf.z = __shfl_up(ce.z, 1); lf.w = __shfl_up(ce.w, 1);
+                rt.x = __shfl_down(ce.x, 1); rt.y = __shfl_down(ce.y, 1);
+                rt.z = __shfl_down(ce.z, 1); rt.w = __shfl_down(ce.w, 1);
+                const size_t row = (size_t)s * S;
+                if (lane == 0) lf = ld4(uin + row + c - 4);
+                if (lane == 63) rt = (c + 4 < S) ? ld4(uin + row + c + 4) : z4;
+                if (store) {
+                    const float v[12] = {lf.x, lf.y, lf.z, lf.w, ce.x, ce.y, ce.z, ce.w, rt.x, rt.y, rt.z, rt.w};
+                    const float pz1[4] = {p1.x, p1.y, p1.z, p1.w}, mz1[4] = {m1.x, m1.y, m1.z, m1.w};
+                    const float pz2[4] = {p2.x, p2.y, p2.z, p2.w}, mz2[4] = {m2.x, m2.y, m2.z, m2.w};
+                    const float pz3[4] = {p3.x, p3.y, p3.z, p3.w}, mz3[4] = {m3.x, m3.y, m3.z, m3.w};
+                    const float pz4[4] = {p4.x, p4.y, p4.z, p4.w}, mz4[4] = {m4.x, m4.y, m4.z, m4.w};
+                    const float4 d4 = ld4(dl + row + c);
+                    const float4 C4 = ld4(Cf + row + c);
+                    const float dv[4] = {d4.x, d4.y, d4.z, d4.w};
+                    const float Cv[4] = {C4.x, C4.y, C4.z, C4.w};
+                    const float azr = R.az[s - kHalo];
+                    const bool damped = tile_xdamp || (azr != 0.0f);
+                    const bool srow = (s == R.srcS);
+                    float un[4], dn[4];
+#pragma unroll
+                    for (int k2 = 0; k2 < 4; ++k2) {
+                        const float u = v[4 + k2];
+                        float lap = c0 * u;
+                        lap = fmaf(cz1, pz1[k2] + mz1[k2], lap);
+                        lap = fmaf(cz2, pz2[k2] + mz2[k2], lap);
+                        lap = fmaf(cz3, pz3[k2] + mz3[k2], lap);
+                        lap = fmaf(cz4, pz4[k2] + mz4[k2], lap);
+                        lap = fmaf(cx1, v[3 + k2] + v[5 + k2], lap);
+                        lap = fmaf(cx2, v[2 + k2] + v[6 + k2], lap);
+                        lap = fmaf(cx3, v[1 + k2] + v[7 + k2], lap);
+                        lap = fmaf(cx4, v[0 + k2] + v[8 + k2], lap);
+                        if (srow && (c + k2 == R.srcC)) lap += fsrc;
+                        float d;
+                        if (damped) {
+                            const float a = azr + axk[k2];
+                            const float inv = __builtin_amdgcn_rcpf(1.0f + a);
+                            d = fmaf(1.0f - a, dv[k2], Cv[k2] * lap) * inv;
+                        } else {
+                            d = fmaf(Cv[k2], lap, dv[k2]);
+                        }
+                        const bool in = (J0 + k2) < R.Nx;
+                        dn[k2] = in ? d : 0.0f;
+                        un[k2] = in ? u + d : 0.0f;
+                    }
+                    st4(uout + row + c, make_float4(un[0], un[1], un[2], un[3]));
+                    st4(dl + row + c, make_float4(dn[0], dn[1], dn[2], dn[3]));
+                    if (s == R.recS) sample_receivers(R, n, J0, ce);
+                }
+            }
+        }
+    }
+}
+
+// Sample u^{n} at the receivers only (used for the last time sample).
+__global__ void k_sample(const RunDesc *__restrict__ runs, int nruns, int n) {
+    const int run = blockIdx.y;
+    if (run >= nruns) return;
+    const RunDesc &R = runs[run];
+    const float *u = (n & 1) ? R.u1 : R.u0;
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < R.nrec; r += gridDim.x * blockDim.x) {
+        const float val = u[(size_t)R.recS * R.S + R.reccol[r] + kHalo];
+        const size_t o = (size_t)n * R.nrec + r;
+        if (R.traces) {
+            R.traces[o] = val;
+        } else {
+            const float res = val - R.obs[o];
+            R.acc[r] += (double)res * (double)res;
+        }
+    }
+}
+
+// fitness[p] = 1/2 sum over the runs of particle p and their receivers of acc.
+// Fixed per-thread order and a fixed tree: the result does not depend on tiling.
+__global__ __launch_bounds__(256) void k_fitness(const RunDesc *__restrict__ runs, const int *__restrict__ prun,
+                                                 float *__restrict__ fitness) {
+    const int p = blockIdx.x;
+    double s = 0.0;
+    for (int run = prun[p]; run < prun[p + 1]; ++run) {
+        const RunDesc &R = runs[run];
+        for (int r = threadIdx.x; r < R.nrec; r += blockDim.x) s += R.acc[r];
+    }
+    __shared__ double red[256];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double f = 0.5 * red[0];
+        fitness[p] = (f == f && f < 1e300) ? (float)f : INFINITY;
+    }
+}
+
+// 1/2 sum (a - b)^2: pass 1 writes one FP64 partial per block, pass 2 sums them.
+__global__ __launch_bounds__(256) void k_misfit_partial(const float *__restrict__ a, const float *__restrict__ b,
+                                                        int64_t n, double *__restrict__ part) {
+    double s = 0.0;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+        const double r = (double)a[k] - (double)b[k];
+        s += r * r;
+    }
+    __shared__ double red[256];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_misfit_final(const double *__restrict__ part, int nparts, float *out) {
+    double s = 0.0;
+    for (int k = threadIdx.x; k < nparts; k += blockDim.x) s += part[k];
+    __shared__ double red[256];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = (float)(0.5 * red[0]);
+}
+
+// ---------------------------------------------------------------------------
+// Batch plans: workspace layout, descriptor upload, launch sequence, graphs
+// ---------------------------------------------------------------------------
+namespace {
+
+struct RunSpec {
+    const empso_problem *p;
+    int particle;      // index into the coefficient fields
+    int shot;
+    const float *obs;  // shot's observed traces or NULL
+    float *traces;     // record output or NULL
+};
+
+struct Layout {
+    size_t runs_off, tiles_off, prun_off, coef_off, nodes_off, C_off, state_off, acc_off, total;
+    size_t hdr_bytes;                 // descriptors + nodes (uploaded each call)
+    std::vector<size_t> C_of_particle;   // byte offsets
+    std::vector<size_t> field_of_run;    // byte offsets of u0 (u1, dl follow)
+    std::vector<size_t> acc_of_run;
+    int ntiles;
+};
+
+static int rows_per_tile_min() { return 18; }
+
+static size_t field_bytes(const empso_problem *p) {
+    return align_up((size_t)(p->Nz + 2 * kHalo) * p->S * sizeof(float), 256);
+}
+
+static int tiles_of(const empso_problem *p, int bz) {
+    const int zt = (p->Nz + bz - 1) / bz;
+    const int xt = (p->Nx + kTileX - 1) / kTileX;
+    return zt * xt;
+}
+
+// particles: problem of each particle, and the runs (particle-major, shot-minor).
+static Layout make_layout(const std::vector<const empso_problem *> &pp, const std::vector<RunSpec> &runs, int Dmax,
+                          int bz) {
+    Layout L;
+    const int np = (int)pp.size();
+    const int nruns = (int)runs.size();
+    int ntiles_max = 0, ntiles = 0;
+    for (const RunSpec &r : runs) {
+        ntiles_max += tiles_of(r.p, rows_per_tile_min());
+        ntiles += tiles_of(r.p, bz);
+    }
+    L.ntiles = ntiles;
+    size_t o = 0;
+    L.runs_off = o; o = align_up(o + sizeof(RunDesc) * nruns, 256);
+    L.tiles_off = o; o = align_up(o + sizeof(int4) * ntiles_max, 256);
+    L.prun_off = o; o = align_up(o + sizeof(int) * (np + 1), 256);
+    L.coef_off = o; o = align_up(o + sizeof(CoefDesc) * np, 256);
+    L.nodes_off = o; o = align_up(o + sizeof(float) * (size_t)np * std::max(Dmax, 1), 256);
+    L.hdr_bytes = o;
+    L.C_off = o;
+    for (int k = 0; k < np; ++k) {
+        L.C_of_particle.push_back(o);
+        o += field_bytes(pp[k]);
+    }
+    L.state_off = o;
+    for (int k = 0; k < nruns; ++k) {
+        L.field_of_run.push_back(o);
+        o += 3 * field_bytes(runs[k].p);
+    }
+    L.acc_off = o;
+    for (int k = 0; k < nruns; ++k) {
+        L.acc_of_run.push_back(o);
+        o = align_up(o + sizeof(double) * runs[k].p->g.nrec, 256);
+    }
+    L.total = o;
+    return L;
+}
+
+struct Plan {
+    // key
+    std::vector<const void *> key_ptrs;
+    std::vector<int> key_ints;
+    // state
+    Layout L;
+    std::vector<unsigned char> host_hdr;   // staging copy of the descriptor header
+    unsigned char *pinned = nullptr;       // pinned staging buffer (hdr_bytes)
+    hipEvent_t upload_done = nullptr;
+    bool upload_pending = false;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t cap_stream = nullptr;
+    ~Plan() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
+        if (upload_done) (void)hipEventDestroy(upload_done);
+        if (pinned) (void)hipHostFree(pinned);
+    }
+};
+
+static std::mutex g_plan_mu;
+static std::vector<Plan *> g_plans;   // small LRU
+static const size_t kMaxPlans = 8;
+
+static int launch_step(int bz, const RunDesc *runs, const int4 *tiles, int ntiles, int n, hipStream_t st) {
+    const int waves = ntiles;
+    int blocks = (waves + 3) / 4;
+    blocks = (blocks + 7) / 8 * 8;
+    switch (bz) {
+        case 18: k_step<18><<<blocks, 256, 0, st>>>(runs, tiles, ntiles, n); break;
+        case 36: k_step<36><<<blocks, 256, 0, st>>>(runs, tiles, ntiles, n); break;
+        case 72: k_step<72><<<blocks, 256, 0, st>>>(runs, tiles, ntiles, n); break;
+        default: return EMPSO_ENOTSUP;
+    }
+    return EMPSO_OK;
+}
+
+// Enqueue the whole evaluation (zero state, coefficients, time loop, final
+// sample, optional reduction) on stream st.
+static int enqueue_all(const Plan &pl, unsigned char *ws, int nruns, int np, int nt, int bz, float *fitness,
+                       hipStream_t st) {
+    const Layout &L = pl.L;
+    const RunDesc *runs = reinterpret_cast<const RunDesc *>(ws + L.runs_off);
+    const int4 *tiles = reinterpret_cast<const int4 *>(ws + L.tiles_off);
+    const int64_t n4 = (int64_t)(L.total - L.state_off) / 16;
+    k_zero<<<2048, 256, 0, st>>>(reinterpret_cast<float4 *>(ws + L.state_off), n4);
+    k_coef<<<dim3(512, np), 256, 0, st>>>(reinterpret_cast<const CoefDesc *>(ws + L.coef_off));
+    for (int n = 0; n < nt - 1; ++n) {
+        int rc = launch_step(bz, runs, tiles, L.ntiles, n, st);
+        if (rc) return rc;
+    }
+    k_sample<<<dim3(8, nruns), 256, 0, st>>>(runs, nruns, nt - 1);
+    if (fitness) k_fitness<<<np, 256, 0, st>>>(runs, reinterpret_cast<const int *>(ws + L.prun_off), fitness);
+    return EMPSO_OK;
+}
+
+// Build the host copy of the descriptor header.
+static void build_header(Plan &pl, unsigned char *ws, const std::vector<const empso_problem *> &pp,
+                         const std::vector<RunSpec> &runs, const std::vector<const float *> &vp_of_particle,
+                         const double *nodes_h, int ld_nodes, int Dmax, int bz) {
+    const Layout &L = pl.L;
+    std::vector<unsigned char> &h = pl.host_hdr;
+    h.assign(L.hdr_bytes, 0);
+    RunDesc *rd = reinterpret_cast<RunDesc *>(h.data() + L.runs_off);
+    int4 *td = reinterpret_cast<int4 *>(h.data() + L.tiles_off);
+    int *prun = reinterpret_cast<int *>(h.data() + L.prun_off);
+    CoefDesc *cd = reinterpret_cast<CoefDesc *>(h.data() + L.coef_off);
+    float *nd = reinterpret_cast<float *>(h.data() + L.nodes_off);
+    const int np = (int)pp.size();
+    for (int k = 0; k < np; ++k) {
+        const empso_problem *p = pp[k];
+        CoefDesc &c = cd[k];
+        c.C = reinterpret_cast<float *>(ws + L.C_of_particle[k]);
+        c.nodes = nullptr;
+        c.vp = vp_of_particle.empty() ? nullptr : vp_of_particle[k];
+        if (nodes_h) {
+            for (int d = 0; d < p->D; ++d) nd[(size_t)k * Dmax + d] = (float)nodes_h[(size_t)k * ld_nodes + d];
+            c.nodes = reinterpret_cast<const float *>(ws + L.nodes_off) + (size_t)k * Dmax;
+        }
+        c.nz = p->g.nz; c.nx = p->g.nx; c.nbl = p->g.nbl; c.ncz = p->g.ncz; c.ncx = p->g.ncx;
+        c.Nz = p->Nz; c.Nx = p->Nx; c.S = p->S;
+        c.dt = (float)p->g.dt;
+    }
+    int cur = -1;
+    for (size_t r = 0; r < runs.size(); ++r) {
+        const RunSpec &rs = runs[r];
+        const empso_problem *p = rs.p;
+        while (cur < rs.particle) prun[++cur] = (int)r;
+        RunDesc &d = rd[r];
+        float *f = reinterpret_cast<float *>(ws + L.field_of_run[r]);
+        const size_t fe = field_bytes(p) / sizeof(float);
+        d.u0 = f; d.u1 = f + fe; d.dl = f + 2 * fe;
+        d.C = reinterpret_cast<const float *>(ws + L.C_of_particle[rs.particle]);
+        d.obs = rs.obs; d.traces = rs.traces;
+        d.acc = reinterpret_cast<double *>(ws + L.acc_of_run[r]);
+        d.wav = p->d_wav; d.az = p->d_az; d.ax = p->d_ax; d.recmap = p->d_recmap; d.reccol = p->d_reccol;
+        d.Nz = p->Nz; d.Nx = p->Nx; d.S = p->S; d.nrec = p->g.nrec;
+        d.recS = p->recI + kHalo;
+        d.srcS = p->srcI[rs.shot] + kHalo;
+        d.srcC = p->srcJ[rs.shot] + kHalo;
+        d.nt = p->g.nt;
+        d.c0 = p->c0;
+        d.cz1 = p->cz[0]; d.cz2 = p->cz[1]; d.cz3 = p->cz[2]; d.cz4 = p->cz[3];
+        d.cx1 = p->cx[0]; d.cx2 = p->cx[1]; d.cx3 = p->cx[2]; d.cx4 = p->cx[3];
+        d.wscale = p->wscale;
+    }
+    while (cur < np) prun[++cur] = (int)runs.size();
+    // tiles: particle, z-strip, x-strip, shot (shot fastest)
+    int nt_ = 0;
+    size_t r0 = 0;
+    for (int k = 0; k < np; ++k) {
+        const empso_problem *p = pp[k];
+        size_t r1 = r0;
+        while (r1 < runs.size() && runs[r1].particle == k) ++r1;
+        const int zt = (p->Nz + bz - 1) / bz, xt = (p->Nx + kTileX - 1) / kTileX;
+        for (int zs = 0; zs < zt; ++zs)
+            for (int xs = 0; xs < xt; ++xs)
+                for (size_t r = r0; r < r1; ++r) td[nt_++] = make_int4((int)r, kHalo + zs * bz, kHalo + xs * kTileX, 0);
+        r0 = r1;
+    }
+}
+
+static int run_plan(Plan *pl, unsigned char *ws, int nruns, int np, int nt, const empso_tuning &tu, float *fitness,
+                    hipStream_t st) {
+    // upload the header through the pinned staging buffer
+    if (!pl->pinned) {
+        EMPSO_HIP(hipHostMalloc(reinterpret_cast<void **>(&pl->pinned), pl->L.hdr_bytes, hipHostMallocDefault));
+        EMPSO_HIP(hipEventCreateWithFlags(&pl->upload_done, hipEventDisableTiming));
+    }
+    if (pl->upload_pending) EMPSO_HIP(hipEventSynchronize(pl->upload_done));
+    std::memcpy(pl->pinned, pl->host_hdr.data(), pl->L.hdr_bytes);
+    EMPSO_HIP(hipMemcpyAsync(ws, pl->pinned, pl->L.hdr_bytes, hipMemcpyHostToDevice, st));
+    EMPSO_HIP(hipEventRecord(pl->upload_done, st));
+    pl->upload_pending = true;
+
+    if (!tu.use_graph) {
+        int rc = enqueue_all(*pl, ws, nruns, np, nt, tu.bz, fitness, st);
+        if (rc) EMPSO_FAIL(rc, "launch failed");
+        EMPSO_HIP(hipGetLastError());
+        return EMPSO_OK;
+    }
+    if (!pl->exec) {
+        if (!pl->cap_stream) EMPSO_HIP(hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking));
+        hipGraph_t graph = nullptr;
+        EMPSO_HIP(hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal));
+        int rc = enqueue_all(*pl, ws, nruns, np, nt, tu.bz, fitness, pl->cap_stream);
+        hipError_t e = hipStreamEndCapture(pl->cap_stream, &graph);
+        if (rc) {
+            if (graph) (void)hipGraphDestroy(graph);
+            EMPSO_FAIL(rc, "launch failed during capture");
+        }
+        if (e != hipSuccess) EMPSO_FAIL(EMPSO_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+        e = hipGraphInstantiate(&pl->exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            pl->exec = nullptr;
+            EMPSO_FAIL(EMPSO_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+        }
+    }
+    EMPSO_HIP(hipGraphLaunch(pl->exec, st));
+    return EMPSO_OK;
+}
+
+static Plan *find_or_make_plan(const std::vector<const void *> &kp, const std::vector<int> &ki, bool *fresh) {
+    for (size_t i = 0; i < g_plans.size(); ++i) {
+        Plan *p = g_plans[i];
+        if (p->key_ptrs == kp && p->key_ints == ki) {
+            g_plans.erase(g_plans.begin() + i);
+            g_plans.push_back(p);
+            *fresh = false;
+            return p;
+        }
+    }
+    if (g_plans.size() >= kMaxPlans) {
+        Plan *old = g_plans.front();
+        // make sure nothing of the evicted plan is still queued before freeing
+        (void)hipDeviceSynchronize();
+        delete old;
+        g_plans.erase(g_plans.begin());
+    }
+    Plan *p = new Plan();
+    p->key_ptrs = kp;
+    p->key_ints = ki;
+    g_plans.push_back(p);
+    *fresh = true;
+    return p;
+}
+
+static bool valid_tuning(const empso_tuning &t) {
+    return t.variant == 0 && (t.bz == 18 || t.bz == 36 || t.bz == 72) && t.tsteps == 1 &&
+           (t.use_graph == 0 || t.use_graph == 1);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Public entry points
+// ---------------------------------------------------------------------------
+extern "C" int empso_vp_from_nodes(const empso_problem *p, int32_t nmodels, const float *nodes_d, float *vp_d,
+                                   empso_stream stream) {
+    clear_error();
+    if (!p || !nodes_d || !vp_d) EMPSO_FAIL(EMPSO_EINVAL, "NULL argument");
+    if (nmodels < 1 || nmodels > 65535) EMPSO_FAIL(EMPSO_EINVAL, "nmodels must be in [1, 65535]");
+    const int64_t npts = (int64_t)p->g.nz * p->g.nx;
+    const int bx = (int)std::min<int64_t>(1024, (npts + 255) / 256);
+    k_vp_from_nodes<<<dim3(bx, nmodels), 256, 0, (hipStream_t)stream>>>(nodes_d, vp_d, p->g.ncz, p->g.ncx, p->g.nz,
+                                                                         p->g.nx);
+    EMPSO_HIP(hipGetLastError());
+    return EMPSO_OK;
+}
+
+extern "C" size_t empso_misfit_workspace_bytes(int64_t n) {
+    (void)n;
+    return 1024 * sizeof(double);
+}
+
+extern "C" int empso_misfit(const float *a_d, const float *b_d, int64_t n, float *out_d, void *ws, size_t ws_bytes,
+                            empso_stream stream) {
+    clear_error();
+    if (!out_d || !ws || (n > 0 && (!a_d || !b_d))) EMPSO_FAIL(EMPSO_EINVAL, "NULL argument");
+    if (n < 0) EMPSO_FAIL(EMPSO_EINVAL, "n must be >= 0");
+    if (ws_bytes < empso_misfit_workspace_bytes(n)) EMPSO_FAIL(EMPSO_EWORKSPACE, "workspace too small");
+    hipStream_t st = (hipStream_t)stream;
+    const int nb = 1024;
+    k_misfit_partial<<<nb, 256, 0, st>>>(a_d, b_d, n, reinterpret_cast<double *>(ws));
+    k_misfit_final<<<1, 256, 0, st>>>(reinterpret_cast<const double *>(ws), nb, out_d);
+    EMPSO_HIP(hipGetLastError());
+    return EMPSO_OK;
+}
+
+static void forward_specs(const empso_problem *p, int32_t shot0, int32_t nsh, float *traces_d,
+                          std::vector<const empso_problem *> &pp, std::vector<RunSpec> &runs) {
+    pp.assign(1, p);
+    runs.clear();
+    for (int s = 0; s < nsh; ++s)
+        runs.push_back(RunSpec{p, 0, shot0 + s, nullptr, traces_d + (size_t)s * p->g.nt * p->g.nrec});
+}
+
+extern "C" size_t empso_forward_workspace_bytes(const empso_problem *p, int32_t nsh) {
+    if (!p || nsh < 1) return 0;
+    std::vector<const empso_problem *> pp;
+    std::vector<RunSpec> runs;
+    forward_specs(p, 0, nsh, nullptr, pp, runs);
+    return make_layout(pp, runs, p->D, 18).total;
+}
+
+extern "C" int empso_forward_shots(const empso_problem *p, const float *vp_d, int32_t shot0, int32_t nsh,
+                                   float *traces_d, void *ws, size_t ws_bytes, empso_stream stream) {
+    clear_error();
+    if (!p || !vp_d || !traces_d || !ws) EMPSO_FAIL(EMPSO_EINVAL, "NULL argument");
+    if (nsh < 1 || shot0 < 0 || shot0 + nsh > p->g.nshots) EMPSO_FAIL(EMPSO_EINVAL, "shot range out of bounds");
+    if (reinterpret_cast<uintptr_t>(ws) % 256) EMPSO_FAIL(EMPSO_EINVAL, "workspace must be 256-byte aligned");
+    if (ws_bytes < empso_forward_workspace_bytes(p, nsh)) EMPSO_FAIL(EMPSO_EWORKSPACE, "workspace too small");
+    hipStream_t st = (hipStream_t)stream;
+    // range check of the model on the host (guarantees the CFL condition)
+    std::vector<float> vh((size_t)p->g.nz * p->g.nx);
+    EMPSO_HIP(hipMemcpyAsync(vh.data(), vp_d, vh.size() * sizeof(float), hipMemcpyDeviceToHost, st));
+    EMPSO_HIP(hipStreamSynchronize(st));
+    for (size_t k = 0; k < vh.size(); ++k)
+        if (!(vh[k] >= (float)p->g.vmin && vh[k] <= (float)p->g.vmax) || !std::isfinite(vh[k]))
+            EMPSO_FAIL(EMPSO_ERANGE, "vp[%zu] = %g outside [%g, %g]", k, (double)vh[k], p->g.vmin, p->g.vmax);
+
+    std::vector<const empso_problem *> pp;
+    std::vector<RunSpec> runs;
+    forward_specs(p, shot0, nsh, traces_d, pp, runs);
+    empso_tuning tu;
+    empso_default_tuning(&tu);
+    tu.use_graph = 0;
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    Plan pl;
+    pl.L = make_layout(pp, runs, p->D, tu.bz);
+    unsigned char *w = reinterpret_cast<unsigned char *>(ws);
+    std::vector<const float *> vps(1, vp_d);
+    build_header(pl, w, pp, runs, vps, nullptr, 0, p->D, tu.bz);
+    int rc = run_plan(&pl, w, (int)runs.size(), 1, p->g.nt, tu, nullptr, st);
+    if (rc) return rc;
+    // the staging buffer is freed with the local plan: wait for the upload
+    EMPSO_HIP(hipEventSynchronize(pl.upload_done));
+    return EMPSO_OK;
+}
+
+static int batch_specs(const empso_problem *const *probs, int32_t nprob, const float *const *obs_d,
+                       const int32_t *pop, int32_t np, std::vector<const empso_problem *> &pp,
+                       std::vector<RunSpec> &runs, int *Dmax) {
+    pp.clear();
+    runs.clear();
+    *Dmax = 0;
+    for (int k = 0; k < np; ++k) {
+        const int q = pop[k];
+        if (q < 0 || q >= nprob) EMPSO_FAIL(EMPSO_EINVAL, "prob_of_particle[%d] = %d out of range", k, q);
+        const empso_problem *p = probs[q];
+        if (!p) EMPSO_FAIL(EMPSO_EINVAL, "probs[%d] is NULL", q);
+        pp.push_back(p);
+        *Dmax = std::max(*Dmax, p->D);
+        for (int s = 0; s < p->g.nshots; ++s)
+            runs.push_back(RunSpec{p, k, s, obs_d ? obs_d[q] + (size_t)s * p->g.nt * p->g.nrec : nullptr, nullptr});
+    }
+    return EMPSO_OK;
+}
+
+extern "C" size_t empso_fitness_workspace_bytes(const empso_problem *const *probs, int32_t nprob,
+                                                const int32_t *pop, int32_t np) {
+    if (!probs || !pop || nprob < 1 || np < 1) return 0;
+    std::vector<const empso_problem *> pp;
+    std::vector<RunSpec> runs;
+    int Dmax;
+    if (batch_specs(probs, nprob, nullptr, pop, np, pp, runs, &Dmax)) return 0;
+    return make_layout(pp, runs, Dmax, 18).total;
+}
+
+extern "C" int empso_fitness_batch(const empso_problem *const *probs, int32_t nprob, const float *const *obs_d,
+                                   const int32_t *pop, int32_t np, const double *nodes_h, int32_t ld_nodes,
+                                   float *fitness_d, void *ws, size_t ws_bytes, const empso_tuning *tuning,
+                                   empso_stream stream) {
+    clear_error();
+    if (!probs || !obs_d || !pop || !nodes_h || !fitness_d || !ws) EMPSO_FAIL(EMPSO_EINVAL, "NULL argument");
+    if (nprob < 1 || np < 1) EMPSO_FAIL(EMPSO_EINVAL, "nprob and np must be >= 1");
+    if (reinterpret_cast<uintptr_t>(ws) % 256) EMPSO_FAIL(EMPSO_EINVAL, "workspace must be 256-byte aligned");
+    for (int q = 0; q < nprob; ++q) {
+        if (!probs[q]) EMPSO_FAIL(EMPSO_EINVAL, "probs[%d] is NULL", q);
+        if (!obs_d[q]) EMPSO_FAIL(EMPSO_EINVAL, "obs_d[%d] is NULL", q);
+        if (probs[q]->g.nt != probs[0]->g.nt) EMPSO_FAIL(EMPSO_ENOTSUP, "all problems of a batch must share nt");
+    }
+    empso_tuning tu;
+    if (tuning) tu = *tuning; else empso_default_tuning(&tu);
+    if (!valid_tuning(tu)) EMPSO_FAIL(EMPSO_ENOTSUP, "unsupported tuning");
+    std::vector<const empso_problem *> pp;
+    std::vector<RunSpec> runs;
+    int Dmax;
+    int rc = batch_specs(probs, nprob, obs_d, pop, np, pp, runs, &Dmax);
+    if (rc) return rc;
+    if (ld_nodes < Dmax) EMPSO_FAIL(EMPSO_EINVAL, "ld_nodes = %d < %d", ld_nodes, Dmax);
+    // range check on the host in FP64: bilinear interpolation is a convex
+    // combination, so every grid velocity then lies in [vmin, vmax] and the
+    // stability condition checked at problem creation holds everywhere.
+    for (int k = 0; k < np; ++k) {
+        const empso_problem *p = pp[k];
+        for (int d = 0; d < p->D; ++d) {
+            const double v = nodes_h[(size_t)k * ld_nodes + d];
+            if (!(v >= p->g.vmin && v <= p->g.vmax))
+                EMPSO_FAIL(EMPSO_ERANGE, "node %d of particle %d = %g outside [%g, %g]", d, k, v, p->g.vmin,
+                           p->g.vmax);
+        }
+    }
+    const size_t need = make_layout(pp, runs, Dmax, 18).total;
+    if (ws_bytes < need) EMPSO_FAIL(EMPSO_EWORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
+
+    std::vector<const void *> kp;
+    std::vector<int> ki;
+    kp.push_back(ws);
+    kp.push_back(fitness_d);
+    for (int q = 0; q < nprob; ++q) kp.push_back(probs[q]);
+    ki.push_back(np);
+    ki.push_back(tu.bz);
+    ki.push_back(tu.use_graph);
+    for (int k = 0; k < np; ++k) ki.push_back(pop[k]);
+
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    bool fresh;
+    Plan *pl = find_or_make_plan(kp, ki, &fresh);
+    if (fresh) pl->L = make_layout(pp, runs, Dmax, tu.bz);
+    unsigned char *w = reinterpret_cast<unsigned char *>(ws);
+    build_header(*pl, w, pp, runs, std::vector<const float *>(), nodes_h, ld_nodes, Dmax, tu.bz);
+    return run_plan(pl, w, (int)runs.size(), np, pp[0]->g.nt, tu, fitness_d, (hipStream_t)stream);
+}

@@ -1,0 +1,200 @@
+"""Python face of the fitness-evaluation library: problems, modelling, misfit, fitness.
+
+Thin wrappers over the C ABI in include/empso.h: they check tensor dtypes,
+devices and shapes, pass data pointers and the current HIP stream, and raise
+EmpsoError on a non-zero status. No arithmetic of the method happens here.
+"""
+import ctypes
+import math
+
+import numpy as np
+import torch
+
+from ._lib import Geometry, ProblemInfo, Tuning, check, lib
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _need(t, dtype, shape=None, name="tensor"):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a CUDA (HIP) tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError("%s must have shape %s, got %s" % (name, tuple(shape), tuple(t.shape)))
+
+
+def stable_dt(vmax, dz, dx):
+    """Stability limit of the scheme (library: empso_stable_dt)."""
+    out = ctypes.c_double()
+    check(lib.empso_stable_dt(float(vmax), float(dz), float(dx), ctypes.byref(out)))
+    return out.value
+
+
+def default_tuning():
+    t = Tuning()
+    check(lib.empso_default_tuning(ctypes.byref(t)))
+    return t
+
+
+def workspace(nbytes, device="cuda"):
+    """A 256-byte aligned device buffer of at least nbytes (uint8 tensor)."""
+    t = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device=device)
+    off = (-t.data_ptr()) % 256
+    return t[off:off + int(nbytes)]
+
+
+class Problem:
+    """A modelling problem (grid, time axis, acquisition, node grid) on the device.
+
+    geom uses the keys of workloads.configs. dt defaults to dt_frac times the
+    library's stability limit at vmax; nt to floor(tmax/dt) + 1.
+    """
+
+    def __init__(self, geom, dt=None, nt=None, vmin=None):
+        if dt is None:
+            dt = geom["dt_frac"] * stable_dt(geom["vmax"], geom["dz"], geom["dx"])
+        if nt is None:
+            nt = int(math.floor(geom["tmax"] / dt + 1e-9)) + 1
+        self.geom = geom
+        self.dt, self.nt = float(dt), int(nt)
+        self._src = np.ascontiguousarray(np.asarray(geom["src"], dtype=np.float64).reshape(-1, 2))
+        self._rec = np.ascontiguousarray(np.asarray(geom["rec"], dtype=np.float64).reshape(-1, 2))
+        lo = np.asarray(geom["node_lo"], dtype=np.float64)
+        if vmin is None:
+            vmin = float(lo.min())
+        g = Geometry()
+        g.nz, g.nx = int(geom["nz"]), int(geom["nx"])
+        g.dz, g.dx = float(geom["dz"]), float(geom["dx"])
+        g.nbl = int(geom["nbl"])
+        g.dt, g.nt, g.f0 = self.dt, self.nt, float(geom["f0"])
+        g.nshots = self._src.shape[0]
+        g.src_zx = self._src.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        g.nrec = self._rec.shape[0]
+        g.rec_zx = self._rec.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        g.ncz, g.ncx = int(geom["ncz"]), int(geom["ncx"])
+        g.vmin, g.vmax = float(vmin), float(geom["vmax"])
+        g.damp_R = float(geom.get("damp_R", 1e-3))
+        h = ctypes.c_void_p()
+        check(lib.empso_problem_create(ctypes.byref(g), ctypes.byref(h)))
+        self.handle = h
+        info = ProblemInfo()
+        check(lib.empso_problem_get_info(h, ctypes.byref(info)))
+        self.info = info
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            lib.empso_problem_destroy(h)
+            self.handle = None
+
+    @property
+    def nshots(self):
+        return self.info.nshots
+
+    @property
+    def nrec(self):
+        return self.info.nrec
+
+    @property
+    def D(self):
+        return self.info.ncz * self.info.ncx
+
+    @property
+    def updates_per_run(self):
+        return int(self.info.updates_per_run)
+
+
+def vp_from_nodes(prob, nodes, out=None):
+    """nodes[nm][ncz*ncx] FP32 (device) -> vp[nm][nz][nx] FP32 (device)."""
+    _need(nodes, torch.float32, name="nodes")
+    nm = nodes.shape[0]
+    if nodes.dim() != 2 or nodes.shape[1] != prob.D:
+        raise ValueError("nodes must be [nm][%d]" % prob.D)
+    if out is None:
+        out = torch.empty((nm, prob.info.nz, prob.info.nx), dtype=torch.float32, device=nodes.device)
+    _need(out, torch.float32, (nm, prob.info.nz, prob.info.nx), "out")
+    check(lib.empso_vp_from_nodes(prob.handle, nm, _ptr(nodes), _ptr(out), _stream()))
+    return out
+
+
+def forward_shots(prob, vp, shot0=0, nsh=None, out=None, ws=None):
+    """Traces [nsh][nt][nrec] FP32 of shots shot0.. of the model vp[nz][nx] (device FP32)."""
+    _need(vp, torch.float32, (prob.info.nz, prob.info.nx), "vp")
+    if nsh is None:
+        nsh = prob.nshots - shot0
+    if out is None:
+        out = torch.empty((nsh, prob.nt, prob.nrec), dtype=torch.float32, device=vp.device)
+    _need(out, torch.float32, (nsh, prob.nt, prob.nrec), "out")
+    need = lib.empso_forward_workspace_bytes(prob.handle, nsh)
+    if ws is None:
+        ws = workspace(need, vp.device)
+    check(lib.empso_forward_shots(prob.handle, _ptr(vp), int(shot0), int(nsh), _ptr(out), _ptr(ws),
+                                  ws.numel(), _stream()))
+    return out
+
+
+def misfit(a, b, out=None, ws=None):
+    """1/2 sum (a - b)^2 (FP32 inputs on the device, FP64 accumulation) -> tensor [1]."""
+    _need(a, torch.float32, name="a")
+    _need(b, torch.float32, tuple(a.shape), "b")
+    if out is None:
+        out = torch.empty(1, dtype=torch.float32, device=a.device)
+    n = a.numel()
+    if ws is None:
+        ws = workspace(lib.empso_misfit_workspace_bytes(n), a.device)
+    check(lib.empso_misfit(_ptr(a), _ptr(b), n, _ptr(out), _ptr(ws), ws.numel(), _stream()))
+    return out
+
+
+class FitnessBatch:
+    """Reusable fitness evaluation of a fixed set of particles over one or more problems.
+
+    probs: list of Problem; obs: list of device FP32 tensors [nshots][nt][nrec];
+    prob_of_particle: problem index per particle. Holds the workspace so that
+    repeated calls reuse the library's cached launch plan (and HIP graph).
+    """
+
+    def __init__(self, probs, obs, prob_of_particle, tuning=None, device="cuda"):
+        self.probs = list(probs)
+        self.obs = list(obs)
+        for p, o in zip(self.probs, self.obs):
+            _need(o, torch.float32, (p.nshots, p.nt, p.nrec), "obs")
+        self.pop = np.ascontiguousarray(np.asarray(prob_of_particle, dtype=np.int32))
+        self.np = int(self.pop.size)
+        self._ph = (ctypes.c_void_p * len(self.probs))(*[p.handle.value for p in self.probs])
+        self._oh = (ctypes.c_void_p * len(self.obs))(*[o.data_ptr() for o in self.obs])
+        self.Dmax = max(p.D for p in self.probs)
+        need = lib.empso_fitness_workspace_bytes(self._ph, len(self.probs), self._pop_ptr(), self.np)
+        if need == 0:
+            raise ValueError("invalid batch")
+        self.ws = workspace(need, device)
+        self.out = torch.empty(self.np, dtype=torch.float32, device=device)
+        self.tuning = tuning if tuning is not None else default_tuning()
+
+    def _pop_ptr(self):
+        return self.pop.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+    @property
+    def updates(self):
+        return sum(self.probs[q].updates_per_run * self.probs[q].nshots for q in self.pop)
+
+    def __call__(self, nodes, tuning=None):
+        """nodes: host float64 [np][D] (row stride Dmax). Returns the device fitness tensor."""
+        x = np.ascontiguousarray(np.asarray(nodes, dtype=np.float64))
+        if x.shape != (self.np, self.Dmax):
+            raise ValueError("nodes must be [%d][%d]" % (self.np, self.Dmax))
+        t = tuning if tuning is not None else self.tuning
+        check(lib.empso_fitness_batch(self._ph, len(self.probs), self._oh, self._pop_ptr(), self.np,
+                                      x.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), self.Dmax,
+                                      _ptr(self.out), _ptr(self.ws), self.ws.numel(), ctypes.byref(t),
+                                      _stream()))
+        return self.out

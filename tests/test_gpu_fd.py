@@ -1,0 +1,193 @@
+"""GPU parity of the HIP fitness path against the FP64 oracle (run on an MI355X).
+
+Bar (from the method's FP32 arithmetic): traces and misfits within 2e-4
+relative L2 of the oracle; tiling, graph replay and repetition are bitwise
+invariant because every grid point is updated by the same instruction
+sequence whatever the tile it falls in.
+"""
+import copy
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import fd as ofd
+from workloads.configs import config, true_model
+
+pytestmark = pytest.mark.gpu
+
+REL = 2e-4
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def gfd():
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    from paper_1905_12795_amd import fd
+    return fd
+
+
+def _pair(gfd, geom):
+    """Oracle and GPU problems with the same dt and nt (taken from the oracle)."""
+    op = ofd.Problem(geom)
+    gp = gfd.Problem(geom, dt=op.dt, nt=op.nt)
+    return op, gp
+
+
+def _rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _fit_close(fg, fo, dobs_norm2):
+    """Misfit bar: relative 2e-4, or in sqrt form near the optimum (both from the trace bar)."""
+    if fo >= 1e-2 * 0.5 * dobs_norm2:
+        return abs(fg - fo) <= REL * fo
+    return abs(np.sqrt(2 * fg) - np.sqrt(2 * fo)) <= REL * np.sqrt(dobs_norm2)
+
+
+def _small_geom():
+    """Several x tiles (Nx = 381 -> 2 tiles of 256) and a ragged z tail."""
+    g = copy.deepcopy(config("tiny"))
+    g.update(nz=61, nx=301, nbl=40, tmax=0.3, ncz=3, ncx=4)
+    g["src"] = [[0.0, 1000.0], [20.0, 2230.0], [0.0, 3000.0]]
+    g["rec"] = [[0.0, 10.0 * j] for j in range(0, 301, 2)]
+    g["node_lo"] = np.full(12, 1400.0)
+    g["node_hi"] = np.full(12, 2700.0)
+    return g
+
+
+def test_vp_from_nodes_matches_oracle(gfd):
+    g = config("realistic")
+    op, gp = _pair(gfd, g)
+    rng = np.random.default_rng(0)
+    nodes = g["node_lo"] + (g["node_hi"] - g["node_lo"]) * rng.random((3, gp.D))
+    vg = gfd.vp_from_nodes(gp, torch.tensor(nodes, dtype=torch.float32, device="cuda")).cpu().numpy()
+    for k in range(3):
+        vo = ofd.vp_from_nodes(nodes[k].astype(np.float32).astype(np.float64), 5, 12, g["nz"], g["nx"])
+        assert np.max(np.abs(vg[k] - vo) / vo) < 2e-6
+
+
+def test_misfit_matches_oracle(gfd):
+    rng = np.random.default_rng(1)
+    a = rng.standard_normal(1_000_003).astype(np.float32)
+    b = rng.standard_normal(1_000_003).astype(np.float32)
+    m = gfd.misfit(torch.tensor(a, device="cuda"), torch.tensor(b, device="cuda")).item()
+    assert m == pytest.approx(ofd.misfit(a, b), rel=1e-6)
+    z = torch.zeros(0, device="cuda")
+    assert gfd.misfit(z, z).item() == 0.0
+
+
+def test_tiny_forward_traces_match_oracle(gfd):
+    g = config("tiny")
+    op, gp = _pair(gfd, g)
+    vp = true_model(g)
+    to = ofd.forward_shots(op, vp)
+    tg = gfd.forward_shots(gp, torch.tensor(vp, dtype=torch.float32, device="cuda")).cpu().numpy()
+    e = _rel(tg, to)
+    _say("tiny forward rel L2", e)
+    assert e <= REL
+
+
+def test_tiny_fitness_matches_oracle(gfd):
+    g = config("tiny")
+    op, gp = _pair(gfd, g)
+    vp = true_model(g)
+    dobs = ofd.forward_shots(op, vp).astype(np.float32)
+    from workloads.models import uniform_particles
+    X = uniform_particles(g["particles"], g["node_lo"], g["node_hi"], g["particle_seed"])
+    fo, _ = ofd.fitness_batch(op, X.astype(np.float32).astype(np.float64), dobs)
+    fb = gfd.FitnessBatch([gp], [torch.tensor(dobs, device="cuda")], [0] * len(X))
+    fg = fb(X).cpu().numpy().astype(np.float64)
+    n2 = float(np.sum(dobs.astype(np.float64) ** 2))
+    _say("tiny fitness rel", np.abs(fg - fo) / fo)
+    for k in range(len(X)):
+        assert _fit_close(fg[k], fo[k], n2), (k, fg[k], fo[k])
+
+
+def test_multi_tile_ragged_traces_and_fitness(gfd):
+    g = _small_geom()
+    op, gp = _pair(gfd, g)
+    rng = np.random.default_rng(5)
+    truth = rng.uniform(1500, 2600, 12)
+    vp = ofd.vp_from_nodes(truth, 3, 4, g["nz"], g["nx"])
+    to = ofd.forward_shots(op, vp)
+    tg = gfd.forward_shots(gp, torch.tensor(vp, dtype=torch.float32, device="cuda")).cpu().numpy()
+    for s in range(3):
+        assert _rel(tg[s], to[s]) <= REL, s
+    dobs = to.astype(np.float32)
+    X = rng.uniform(1400, 2700, (5, 12))
+    X[0] = truth
+    fo, _ = ofd.fitness_batch(op, X.astype(np.float32).astype(np.float64), dobs)
+    fb = gfd.FitnessBatch([gp], [torch.tensor(dobs, device="cuda")], [0] * 5)
+    n2 = float(np.sum(dobs.astype(np.float64) ** 2))
+    for t in (dict(bz=18, use_graph=0), dict(bz=36, use_graph=1), dict(bz=72, use_graph=1)):
+        tu = gfd.default_tuning()
+        tu.bz, tu.use_graph = t["bz"], t["use_graph"]
+        fg = fb(X, tuning=tu).cpu().numpy().astype(np.float64)
+        for k in range(5):
+            assert _fit_close(fg[k], fo[k], n2), (t, k, fg[k], fo[k])
+
+
+def test_tiling_graph_and_repeat_are_bitwise_invariant(gfd):
+    g = _small_geom()
+    op, gp = _pair(gfd, g)
+    rng = np.random.default_rng(6)
+    dobs = torch.tensor(rng.standard_normal((3, gp.nt, gp.nrec)).astype(np.float32) * 1e-3, device="cuda")
+    X = rng.uniform(1400, 2700, (7, 12))
+    fb = gfd.FitnessBatch([gp], [dobs], [0] * 7)
+    outs = []
+    for bz in (18, 36, 72):
+        for graph in (0, 1):
+            tu = gfd.default_tuning()
+            tu.bz, tu.use_graph = bz, graph
+            for _ in range(2):
+                outs.append(fb(X, tuning=tu).clone())
+    for o in outs[1:]:
+        assert torch.equal(o, outs[0])
+
+
+def test_mixed_sizes_in_one_batch_equal_separate_batches(gfd):
+    g1 = _small_geom()
+    g2 = copy.deepcopy(g1)
+    g2.update(nz=45, nx=201)
+    g2["src"] = [[0.0, 500.0], [0.0, 1500.0]]
+    g2["rec"] = [[0.0, 10.0 * j] for j in range(0, 201, 3)]
+    o1 = ofd.Problem(g1)
+    p1 = gfd.Problem(g1, dt=o1.dt, nt=o1.nt)
+    p2 = gfd.Problem(g2, dt=o1.dt, nt=o1.nt)
+    rng = np.random.default_rng(7)
+    d1 = torch.tensor(rng.standard_normal((3, p1.nt, p1.nrec)).astype(np.float32) * 1e-3, device="cuda")
+    d2 = torch.tensor(rng.standard_normal((2, p2.nt, p2.nrec)).astype(np.float32) * 1e-3, device="cuda")
+    pop = [0, 1, 1, 0, 1]
+    X = rng.uniform(1400, 2700, (5, 12))
+    mixed = gfd.FitnessBatch([p1, p2], [d1, d2], pop)(X).cpu()
+    a = gfd.FitnessBatch([p1], [d1], [0, 0])(X[[0, 3]]).cpu()
+    b = gfd.FitnessBatch([p2], [d2], [0, 0, 0])(X[[1, 2, 4]]).cpu()
+    assert torch.equal(mixed[[0, 3]], a)
+    assert torch.equal(mixed[[1, 2, 4]], b)
+
+
+def test_error_paths(gfd):
+    from paper_1905_12795_amd._lib import EmpsoError
+    g = config("tiny")
+    op, gp = _pair(gfd, g)
+    d = torch.zeros((1, gp.nt, gp.nrec), device="cuda")
+    fb = gfd.FitnessBatch([gp], [d], [0, 0])
+    X = np.full((2, 6), 2000.0)
+    X[1, 3] = 2800.0                                      # above vmax
+    with pytest.raises(EmpsoError) as ei:
+        fb(X)
+    assert ei.value.status == -3
+    X[1, 3] = np.nan
+    with pytest.raises(EmpsoError):
+        fb(X)
+    vp = torch.full((g["nz"], g["nx"]), 3000.0, device="cuda")
+    with pytest.raises(EmpsoError) as ei:
+        gfd.forward_shots(gp, vp)
+    assert ei.value.status == -3

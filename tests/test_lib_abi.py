@@ -1,0 +1,101 @@
+"""The C ABI library loads without a GPU, exports every declared symbol, and
+rejects invalid requests on the host before any device work."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "empso.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(empso_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1905_12795_amd import _lib
+    return _lib
+
+
+def test_every_declared_symbol_is_exported_and_bound(L):
+    names = _declared()
+    assert len(names) >= 14
+    raw = ctypes.CDLL(L.LIB_PATH)
+    for n in names:
+        assert hasattr(raw, n), n
+        assert n in L.SIGNATURES, n
+
+
+def test_status_strings(L):
+    for code, name in L.STATUS.items():
+        assert L.lib.empso_status_string(code).decode() == name
+
+
+def test_stable_dt_host(L):
+    out = ctypes.c_double()
+    assert L.lib.empso_stable_dt(6000.0, 10.0, 10.0, ctypes.byref(out)) == 0
+    assert out.value == pytest.approx(2.0 / (6000.0 * np.sqrt(2048 / 315 * 0.02)), rel=1e-14)
+    assert L.lib.empso_stable_dt(-1.0, 10.0, 10.0, ctypes.byref(out)) == -1
+    assert L.lib.empso_stable_dt(1.0, 10.0, 10.0, None) == -1
+
+
+def _geom(L, **kw):
+    src = np.array([[0.0, 500.0]])
+    rec = np.array([[0.0, 10.0 * j] for j in range(101)])
+    g = L.Geometry()
+    g.nz = g.nx = 101
+    g.dz = g.dx = 10.0
+    g.nbl = 40
+    g.dt = 0.4 * 0.554632 * 10 / 2700
+    g.nt = 100
+    g.f0 = 10.0
+    g.nshots, g.nrec = 1, 101
+    g.ncz, g.ncx = 2, 3
+    g.vmin, g.vmax, g.damp_R = 1400.0, 2700.0, 1e-3
+    for k, v in kw.items():
+        if k == "src":
+            src = np.asarray(v, dtype=np.float64)
+        elif k == "rec":
+            rec = np.asarray(v, dtype=np.float64)
+        else:
+            setattr(g, k, v)
+    g.nshots, g.nrec = len(src), len(rec)
+    g._keep = (src, rec)
+    g.src_zx = src.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    g.rec_zx = rec.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    return g
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(dt=1.01 * 0.554632 * 10 / 2700), -2),           # above the stability limit
+    (dict(nz=1), -1),
+    (dict(ncz=1), -1),
+    (dict(vmin=3000.0), -1),                              # vmin > vmax
+    (dict(damp_R=1.5), -1),
+    (dict(rec=[[0.0, 15.0]]), -6),                        # receiver off the grid
+    (dict(rec=[[0.0, 10.0], [10.0, 20.0]]), -6),          # receivers on two rows
+    (dict(rec=[[0.0, 10.0], [0.0, 10.0]]), -6),           # two receivers on one point
+    (dict(src=[[0.0, 2000.0]]), -6),                      # source outside the grid
+])
+def test_problem_create_rejects_on_host(L, kw, status):
+    g = _geom(L, **kw)
+    h = ctypes.c_void_p(123)
+    assert L.lib.empso_problem_create(ctypes.byref(g), ctypes.byref(h)) == status
+    assert h.value is None
+    assert len(L.lib.empso_last_error()) > 0
+
+
+def test_null_arguments(L):
+    assert L.lib.empso_problem_create(None, None) == -1
+    assert L.lib.empso_fitness_batch(None, 1, None, None, 1, None, 1, None, None, 0, None, None) == -1
+    assert L.lib.empso_misfit(None, None, 10, None, None, 0, None) == -1
+    assert L.lib.empso_fitness_workspace_bytes(None, 1, None, 1) == 0
+    t = L.Tuning()
+    assert L.lib.empso_default_tuning(ctypes.byref(t)) == 0
+    assert t.tsteps >= 1 and t.bz > 0
