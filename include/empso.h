@@ -100,11 +100,13 @@ typedef struct {
     int64_t updates_per_run; /* Nz * Nx * (nt - 1): point updates of one shot           */
 } empso_problem_info;
 
-/* Tuning of the finite-difference kernels (chosen by empso_autotune). */
+/* Tuning of the finite-difference kernels. Every valid tuning gives
+ * bit-identical results; only the speed changes. */
 typedef struct {
-    int32_t variant;         /* kernel family: 0 = single-step z-march                  */
-    int32_t bz;              /* rows per tile                                            */
-    int32_t tsteps;          /* time steps per launch (temporal-blocking depth)         */
+    int32_t variant;         /* reserved, 0                                             */
+    int32_t bz;              /* output rows per tile: 20, 40, 80 or 160                  */
+    int32_t tsteps;          /* time steps per launch (temporal-blocking depth): 1..3   */
+    int32_t prefetch;        /* rows of u requested ahead of use: 1                     */
     int32_t use_graph;       /* 1: replay the time loop from a captured HIP graph       */
 } empso_tuning;
 
@@ -145,9 +147,11 @@ size_t empso_forward_workspace_bytes(const empso_problem *prob, int32_t nsh);
  * (device, FP32; copied once to the host for the range check, so this call
  * waits for the stream) and write traces_d[nsh][nt][nrec] (device, FP32).
  * The model is extended into the absorbing layer by nearest-value copy.
- * ERANGE if a velocity lies outside [vmin, vmax]. */
+ * ERANGE if a velocity lies outside [vmin, vmax]. tuning may be NULL (library
+ * default; the graph flag is ignored). The traces do not depend on the tuning. */
 int empso_forward_shots(const empso_problem *prob, const float *vp_d, int32_t shot0, int32_t nsh,
-                        float *traces_d, void *ws, size_t ws_bytes, empso_stream stream);
+                        float *traces_d, void *ws, size_t ws_bytes, const empso_tuning *tuning,
+                        empso_stream stream);
 
 /* Workspace bytes for empso_misfit over n elements. */
 size_t empso_misfit_workspace_bytes(int64_t n);

@@ -40,7 +40,7 @@ class ProblemInfo(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int32), ("bz", ctypes.c_int32),
-                ("tsteps", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+                ("tsteps", ctypes.c_int32), ("prefetch", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -59,7 +59,7 @@ SIGNATURES = {
     "empso_vp_from_nodes": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, _vp, _vp]),
     "empso_forward_workspace_bytes": (ctypes.c_size_t, [_vp, ctypes.c_int32]),
     "empso_forward_shots": (ctypes.c_int, [_vp, _vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp,
-                                           ctypes.c_size_t, _vp]),
+                                           ctypes.c_size_t, _P(Tuning), _vp]),
     "empso_misfit_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int64]),
     "empso_misfit": (ctypes.c_int, [_vp, _vp, ctypes.c_int64, _vp, _vp, ctypes.c_size_t, _vp]),
     "empso_fitness_workspace_bytes": (ctypes.c_size_t, [_P(_vp), ctypes.c_int32, _P(ctypes.c_int32),

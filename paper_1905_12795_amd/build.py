@@ -13,6 +13,8 @@ HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # packed FP32 instructions stay off (hand-written or compiler-generated)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # no implicit multiply-add fusion: every kernel variant rounds identically
+    "-ffp-contract=off",
     "-Wall", "-Wno-unused-function",
 ]
 

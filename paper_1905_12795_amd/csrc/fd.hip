@@ -59,10 +59,12 @@ static const double kW[5] = {-205.0 / 72.0, 8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, 
 // |symbol| at the Nyquist wavenumber: |w0 + 2 sum_k w_k (-1)^k| = 2048/315.
 static const double kSymbolMax = 2048.0 / 315.0;
 
-static const int kHalo = 4;        // zero ring around the padded grid
+static const int kRing = 16;       // zero ring (rows and columns) around the padded grid
 static const int kLanesX = 64;     // lanes per wavefront
 static const int kColsPerLane = 4;
-static const int kTileX = kLanesX * kColsPerLane;
+static const int kTileX = kLanesX * kColsPerLane;   // columns loaded by one wavefront
+static const int kQueue = 10;      // row-queue slots per level (9 stencil rows + 1 prefetch)
+static const int kMaxT = 3;        // deepest temporal blocking (4 kMaxT <= kRing)
 
 }  // namespace empso
 
@@ -164,7 +166,7 @@ extern "C" int empso_problem_create(const empso_geometry *gp, empso_problem **ou
     p->g.rec_zx = nullptr;
     p->Nz = (int)Nz64;
     p->Nx = (int)Nx64;
-    p->S = (int)align_up((size_t)p->Nx + 2 * kHalo, 64);
+    p->S = (int)align_up((size_t)p->Nx + 2 * kRing, 64);
     p->D = g.ncz * g.ncx;
     for (int s = 0; s < g.nshots; ++s) {
         int i, j;
@@ -271,8 +273,9 @@ extern "C" int empso_problem_get_info(const empso_problem *p, empso_problem_info
 extern "C" int empso_default_tuning(empso_tuning *t) {
     if (!t) EMPSO_FAIL(EMPSO_EINVAL, "NULL argument");
     t->variant = 0;
-    t->bz = 36;
+    t->bz = 40;
     t->tsteps = 1;
+    t->prefetch = 1;
     t->use_graph = 1;
     return EMPSO_OK;
 }
@@ -281,7 +284,7 @@ extern "C" int empso_default_tuning(empso_tuning *t) {
 // Device-side descriptors
 // ---------------------------------------------------------------------------
 struct RunDesc {
-    float *u0, *u1, *dl;        // fields (storage base, ring included)
+    float *u[2], *d[2];         // ping-pong fields u and delta (storage base, ring included)
     const float *C;             // coefficient field of the particle
     const float *obs;           // [nt][nrec] observed traces of this shot (fitness mode)
     float *traces;              // [nt][nrec] output (record mode) or NULL
@@ -289,6 +292,7 @@ struct RunDesc {
     const float *wav, *az, *ax;
     const int *recmap, *reccol;
     int Nz, Nx, S, nrec, recS, srcS, srcC, nt;
+    int junk;                   // stored row that absorbs discarded stores (never read)
     float c0, cz1, cz2, cz3, cz4, cx1, cx2, cx3, cx4, wscale;
 };
 
@@ -303,8 +307,6 @@ struct CoefDesc {
 // ---------------------------------------------------------------------------
 // Kernels
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ float4 ld4(const float *p) { return *reinterpret_cast<const float4 *>(p); }
-__device__ __forceinline__ void st4(float *p, float4 v) { *reinterpret_cast<float4 *>(p) = v; }
 
 // Bilinear interpolation of a regular node grid at physical grid point (i, j).
 // Cell indices come from exact integer division so that node rows/columns that
@@ -335,11 +337,11 @@ __global__ void k_vp_from_nodes(const float *__restrict__ nodes, float *__restri
 // Coefficient field C = (v dt)^2 on the stored layout (zero outside the padded grid).
 __global__ void k_coef(const CoefDesc *__restrict__ cds) {
     const CoefDesc cd = cds[blockIdx.y];
-    const int rows = cd.Nz + 2 * kHalo;
+    const int rows = cd.Nz + 2 * kRing;
     const int64_t npts = (int64_t)rows * cd.S;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < npts; k += (int64_t)gridDim.x * blockDim.x) {
         const int s = (int)(k / cd.S), c = (int)(k - (int64_t)s * cd.S);
-        const int I = s - kHalo, J = c - kHalo;
+        const int I = s - kRing, J = c - kRing;
         float val = 0.0f;
         if (I >= 0 && I < cd.Nz && J >= 0 && J < cd.Nx) {
             const int i = min(max(I - cd.nbl, 0), cd.nz - 1);
@@ -366,140 +368,243 @@ __device__ __forceinline__ int xcd_logical_block(int b, int nblocks) {
     return (b & 7) * per + (b >> 3);
 }
 
+// Scalar and vector accesses through explicit address spaces: pointers read
+// from descriptors are generic, and generic (flat) accesses count against the
+// LDS counter too, so every wait would also wait for all memory in flight.
+template <typename T>
+__device__ __forceinline__ T gld(const T *p) { return *(const __attribute__((address_space(1))) T *)p; }
+template <typename T>
+__device__ __forceinline__ void gst(T *p, T v) { *(__attribute__((address_space(1))) T *)p = v; }
+// wave-uniform address: scalar load through the constant address space
+template <typename T>
+__device__ __forceinline__ T sld(const T *p) { return *(const __attribute__((address_space(4))) T *)p; }
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) const v4f gcv4f;
+typedef __attribute__((address_space(1))) v4f gv4f;
+__device__ __forceinline__ float4 gld4(const float *p) {
+    const v4f v = *(gcv4f *)p;
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void gst4(float *p, float4 v) {
+    v4f w;
+    w.x = v.x; w.y = v.y; w.z = v.z; w.w = v.w;
+    *(gv4f *)p = w;
+}
+
+// Accumulate (or record) the receiver samples held by one lane: u4 are the
+// values of u^n at padded columns J0 .. J0+3 of the receiver row.
 __device__ __forceinline__ void sample_receivers(const RunDesc &R, int n, int J0, const float4 ce) {
     const float u4[4] = {ce.x, ce.y, ce.z, ce.w};
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int J = J0 + k;
-        if (J < R.Nx) {
-            const int r = R.recmap[J];
+        if (J >= 0 && J < R.Nx) {
+            const int r = gld(R.recmap + J);
             if (r >= 0) {
                 const size_t o = (size_t)n * R.nrec + r;
                 if (R.traces) {
-                    R.traces[o] = u4[k];
+                    gst(R.traces + o, u4[k]);
                 } else {
-                    const float res = u4[k] - R.obs[o];
-                    R.acc[r] += (double)res * (double)res;
+                    const float res = u4[k] - gld(R.obs + o);
+                    gst(R.acc + r, gld(R.acc + r) + (double)res * (double)res);
                 }
             }
         }
     }
 }
 
-// One time step n -> n+1 for every tile. Each wavefront owns one tile.
-template <int BZ>
-__global__ __launch_bounds__(256) void k_step(const RunDesc *__restrict__ runs, const int4 *__restrict__ tiles,
-                                              int ntiles, int n) {
+// Whole-wavefront lane shifts (DPP wave_shr:1 / wave_shl:1): the value of
+// lane-1 / lane+1. The lane without a source (0 resp. 63) gets 0.
+__device__ __forceinline__ float from_lane_below(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float from_lane_above(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
+}
+
+// T time steps n -> n+T for every tile, all levels in registers.
+//
+// A wavefront loads 256 columns (4 per lane) and owns the central 256 - 8T of
+// them: the level-t result is exact 4t columns in from either edge, so
+// neighbouring tiles overlap by 8T columns and recompute them. In z, the
+// wavefront owns M * 10 rows and marches down from 4T rows above them. In
+// each step of the march, level 1 updates row r from u^n rows r-4 .. r+4 (a
+// queue of 10 slots with one row requested ahead) and delta^n(r); level t
+// updates row r - 4(t-1) from the 9-row queue of level t-1's results and the
+// delta that level t-1 produced for that row 4 steps earlier (a 5-slot queue).
+// Level T writes u^{n+T} and delta^{n+T} for owned rows and columns; every
+// other store is sent to the junk row, so the loop body has no branches.
+// Points outside the padded grid are forced to zero at every level.
+// Receiver samples of each level (u^{n+t-1} on the receiver row) are kept in
+// registers and accumulated after the march by the owning lanes.
+template <int M, int T>
+__global__ __launch_bounds__(256) void k_tb(const RunDesc *__restrict__ runs, const int4 *__restrict__ tiles,
+                                            int ntiles, int n, int par) {
+    constexpr int NS = kQueue;
+    constexpr int ND = 5;
+    constexpr int BZ = M * NS;
+    constexpr int FILL = 8 * (T - 1);
+    constexpr int TQ = T > 1 ? T - 1 : 1;
     const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
     const int tix = __builtin_amdgcn_readfirstlane(lb * 4 + (int)(threadIdx.x >> 6));
     if (tix >= ntiles) return;
     const int lane = threadIdx.x & 63;
     const int4 t = tiles[tix];
-    const RunDesc &R = runs[t.x];
+    const RunDesc R = runs[t.x];
     const int S = R.S;
-    const float *__restrict__ uin = (n & 1) ? R.u1 : R.u0;
-    float *__restrict__ uout = (n & 1) ? R.u0 : R.u1;
-    float *__restrict__ dl = R.dl;
-    const float *__restrict__ Cf = R.C;
-    const int c = t.z + 4 * lane;          // stored column of this lane's first element
-    const bool live = c < S;                // inside the stored row
-    const bool store = c < R.Nx + kHalo;    // holds at least one grid column
-    const int J0 = c - kHalo;
+    const int top = kRing, bot = R.Nz + kRing;      // stored rows of the padded grid
+    const int rmax = R.Nz + 2 * kRing - 1;          // last readable stored row
+    // (selects, not R.u[par]: a runtime index would move R to scratch memory)
+    const float *uin = par ? R.u[1] : R.u[0];
+    const float *din = par ? R.d[1] : R.d[0];
+    float *uout = par ? R.u[0] : R.u[1];
+    float *dout = par ? R.d[0] : R.d[1];
+    const float *Cf = R.C;
+    const int c = t.z + 4 * lane;                   // stored column of this lane's first element
+    const int cc = min(c, S - 4);                   // past the row: its zero tail
+    const int J0 = c - kRing;
+    const bool own = (lane >= T) && (lane < 64 - T);
     const int s0 = t.y;
-    const int s1 = min(s0 + BZ, R.Nz + kHalo);
+    const int s1 = min(s0 + BZ, bot);
+    const size_t junk = (size_t)R.junk * S + cc;
 
     float axk[4];
+    bool inx[4];
     bool xdamp = false;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        axk[k] = (J0 + k < R.Nx) ? R.ax[J0 + k] : 0.0f;
+        const int J = J0 + k;
+        inx[k] = (J >= 0) && (J < R.Nx);
+        axk[k] = inx[k] ? gld(R.ax + J) : 0.0f;
         xdamp |= axk[k] != 0.0f;
     }
     const bool tile_xdamp = __any(xdamp);
-    const float c0 = R.c0, cz1 = R.cz1, cz2 = R.cz2, cz3 = R.cz3, cz4 = R.cz4;
-    const float cx1 = R.cx1, cx2 = R.cx2, cx3 = R.cx3, cx4 = R.cx4;
-    const float fsrc = R.wav[n] * R.wscale;
-    const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    float fsrc[T];
+#pragma unroll
+    for (int l = 0; l < T; ++l) fsrc[l] = sld(R.wav + min(n + l, R.nt - 1)) * R.wscale;
 
-    float4 q[9];
+    const int rs = s0 - 4 * (T - 1);                // level-1 row of the first march step
+    float4 q0[NS], qu[TQ][NS], qd[TQ][ND], dq[2], cq[T][2], rec[T];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) q[j] = live ? ld4(uin + (size_t)(s0 - 4 + j) * S + c) : z4;
+    for (int j = 0; j < 9; ++j) q0[j] = gld4(uin + (size_t)min(rs - 4 + j, rmax) * S + cc);
+    dq[0] = gld4(din + (size_t)min(rs, rmax) * S + cc);
+#pragma unroll
+    for (int l = 0; l < T; ++l) {
+        cq[l][0] = gld4(Cf + (size_t)min(max(rs - 4 * l, 0), rmax) * S + cc);
+        rec[l] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    // the level queues fill during the first march steps; start them at zero
+#pragma unroll
+    for (int l = 0; l < TQ; ++l) {
+#pragma unroll
+        for (int j = 0; j < NS; ++j) qu[l][j] = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+        for (int j = 0; j < ND; ++j) qd[l][j] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
 
-    for (int sb = s0; sb < s1; sb += 9) {
+    // One march step: k = (step index) mod 10, known at compile time.
+    auto step = [&](const int k, const int r1) {
+        q0[(k + 9) % NS] = gld4(uin + (size_t)min(r1 + 5, rmax) * S + cc);
+        dq[(k + 1) & 1] = gld4(din + (size_t)min(r1 + 1, rmax) * S + cc);
 #pragma unroll
-        for (int k = 0; k < 9; ++k) {
-            const int s = sb + k;
-            if (s < s1) {
-                q[(k + 8) % 9] = live ? ld4(uin + (size_t)(s + 4) * S + c) : z4;
-                const float4 ce = q[(k + 4) % 9];
-                const float4 p1 = q[(k + 3) % 9], m1 = q[(k + 5) % 9];
-                const float4 p2 = q[(k + 2) % 9], m2 = q[(k + 6) % 9];
-                const float4 p3 = q[(k + 1) % 9], m3 = q[(k + 7) % 9];
-                const float4 p4 = q[(k + 0) % 9], m4 = q[(k + 8) % 9];
-                float4 lf, rt;
-                lf.x = __shfl_up(ce.x, 1); lf.y = __shfl_up(ce.y, 1);
-                lf.z = __shfl_up(ce.z, 1); lf.w = __shfl_up(ce.w, 1);
-                rt.x = __shfl_down(ce.x, 1); rt.y = __shfl_down(ce.y, 1);
-                rt.z = __shfl_down(ce.z, 1); rt.w = __shfl_down(ce.w, 1);
-                const size_t row = (size_t)s * S;
-                if (lane == 0) lf = ld4(uin + row + c - 4);
-                if (lane == 63) rt = (c + 4 < S) ? ld4(uin + row + c + 4) : z4;
-                if (store) {
-                    const float v[12] = {lf.x, lf.y, lf.z, lf.w, ce.x, ce.y, ce.z, ce.w, rt.x, rt.y, rt.z, rt.w};
-                    const float pz1[4] = {p1.x, p1.y, p1.z, p1.w}, mz1[4] = {m1.x, m1.y, m1.z, m1.w};
-                    const float pz2[4] = {p2.x, p2.y, p2.z, p2.w}, mz2[4] = {m2.x, m2.y, m2.z, m2.w};
-                    const float pz3[4] = {p3.x, p3.y, p3.z, p3.w}, mz3[4] = {m3.x, m3.y, m3.z, m3.w};
-                    const float pz4[4] = {p4.x, p4.y, p4.z, p4.w}, mz4[4] = {m4.x, m4.y, m4.z, m4.w};
-                    const float4 d4 = ld4(dl + row + c);
-                    const float4 C4 = ld4(Cf + row + c);
-                    const float dv[4] = {d4.x, d4.y, d4.z, d4.w};
-                    const float Cv[4] = {C4.x, C4.y, C4.z, C4.w};
-                    const float azr = R.az[s - kHalo];
-                    const bool damped = tile_xdamp || (azr != 0.0f);
-                    const bool srow = (s == R.srcS);
-                    float un[4], dn[4];
+        for (int l = 0; l < T; ++l)
+            cq[l][(k + 1) & 1] = gld4(Cf + (size_t)min(max(r1 + 1 - 4 * l, 0), rmax) * S + cc);
+        float4 un = make_float4(0.f, 0.f, 0.f, 0.f), dn = un;
 #pragma unroll
-                    for (int k2 = 0; k2 < 4; ++k2) {
-                        const float u = v[4 + k2];
-                        float lap = c0 * u;
-                        lap = fmaf(cz1, pz1[k2] + mz1[k2], lap);
-                        lap = fmaf(cz2, pz2[k2] + mz2[k2], lap);
-                        lap = fmaf(cz3, pz3[k2] + mz3[k2], lap);
-                        lap = fmaf(cz4, pz4[k2] + mz4[k2], lap);
-                        lap = fmaf(cx1, v[3 + k2] + v[5 + k2], lap);
-                        lap = fmaf(cx2, v[2 + k2] + v[6 + k2], lap);
-                        lap = fmaf(cx3, v[1 + k2] + v[7 + k2], lap);
-                        lap = fmaf(cx4, v[0 + k2] + v[8 + k2], lap);
-                        if (srow && (c + k2 == R.srcC)) lap += fsrc;
-                        float d;
-                        if (damped) {
-                            const float a = azr + axk[k2];
-                            const float inv = __builtin_amdgcn_rcpf(1.0f + a);
-                            d = fmaf(1.0f - a, dv[k2], Cv[k2] * lap) * inv;
-                        } else {
-                            d = fmaf(Cv[k2], lap, dv[k2]);
-                        }
-                        const bool in = (J0 + k2) < R.Nx;
-                        dn[k2] = in ? d : 0.0f;
-                        un[k2] = in ? u + d : 0.0f;
-                    }
-                    st4(uout + row + c, make_float4(un[0], un[1], un[2], un[3]));
-                    st4(dl + row + c, make_float4(dn[0], dn[1], dn[2], dn[3]));
-                    if (s == R.recS) sample_receivers(R, n, J0, ce);
+        for (int l = 0; l < T; ++l) {
+            const float4 *src = (l == 0) ? q0 : qu[l > 0 ? l - 1 : 0];
+            const float4 ce = src[(k + 4) % NS];
+            const float4 p1 = src[(k + 3) % NS], m1 = src[(k + 5) % NS];
+            const float4 p2 = src[(k + 2) % NS], m2 = src[(k + 6) % NS];
+            const float4 p3 = src[(k + 1) % NS], m3 = src[(k + 7) % NS];
+            const float4 p4 = src[(k + 0) % NS], m4 = src[(k + 8) % NS];
+            const float4 d4 = (l == 0) ? dq[k & 1] : qd[l > 0 ? l - 1 : 0][(k + 1) % ND];
+            const float4 C4 = cq[l][k & 1];
+            const int r = r1 - 4 * l;
+            const bool rowin = (r >= top) && (r < bot);
+            const float v[12] = {from_lane_below(ce.x), from_lane_below(ce.y),
+                                 from_lane_below(ce.z), from_lane_below(ce.w),
+                                 ce.x, ce.y, ce.z, ce.w,
+                                 from_lane_above(ce.x), from_lane_above(ce.y),
+                                 from_lane_above(ce.z), from_lane_above(ce.w)};
+            const float pz1[4] = {p1.x, p1.y, p1.z, p1.w}, mz1[4] = {m1.x, m1.y, m1.z, m1.w};
+            const float pz2[4] = {p2.x, p2.y, p2.z, p2.w}, mz2[4] = {m2.x, m2.y, m2.z, m2.w};
+            const float pz3[4] = {p3.x, p3.y, p3.z, p3.w}, mz3[4] = {m3.x, m3.y, m3.z, m3.w};
+            const float pz4[4] = {p4.x, p4.y, p4.z, p4.w}, mz4[4] = {m4.x, m4.y, m4.z, m4.w};
+            const float dv[4] = {d4.x, d4.y, d4.z, d4.w};
+            const float Cv[4] = {C4.x, C4.y, C4.z, C4.w};
+            const float azr = sld(R.az + min(max(r - top, 0), R.Nz - 1));
+            const bool damped = tile_xdamp || (azr != 0.0f);
+            const bool srow = (r == R.srcS);
+            float uo[4], dd[4];
+#pragma unroll
+            for (int k2 = 0; k2 < 4; ++k2) {
+                const float u = v[4 + k2];
+                float lap = R.c0 * u;
+                lap = fmaf(R.cz1, pz1[k2] + mz1[k2], lap);
+                lap = fmaf(R.cz2, pz2[k2] + mz2[k2], lap);
+                lap = fmaf(R.cz3, pz3[k2] + mz3[k2], lap);
+                lap = fmaf(R.cz4, pz4[k2] + mz4[k2], lap);
+                lap = fmaf(R.cx1, v[3 + k2] + v[5 + k2], lap);
+                lap = fmaf(R.cx2, v[2 + k2] + v[6 + k2], lap);
+                lap = fmaf(R.cx3, v[1 + k2] + v[7 + k2], lap);
+                lap = fmaf(R.cx4, v[0 + k2] + v[8 + k2], lap);
+                lap += (srow && (c + k2 == R.srcC)) ? fsrc[l] : 0.0f;
+                // The damped form reduces bit for bit to the undamped one when
+                // a = 0 ((1-a) dv = dv, rcp(1) = 1), so the result of a point
+                // does not depend on which branch its tile takes.
+                float d;
+                if (damped) {
+                    const float a = azr + axk[k2];
+                    const float inv = __builtin_amdgcn_rcpf(1.0f + a);
+                    d = fmaf(Cv[k2], lap, (1.0f - a) * dv[k2]) * inv;
+                } else {
+                    d = fmaf(Cv[k2], lap, dv[k2]);
                 }
+                const bool in = rowin && inx[k2];
+                dd[k2] = in ? d : 0.0f;
+                uo[k2] = in ? u + d : 0.0f;
+            }
+            if (r == R.recS) rec[l] = ce;
+            un = make_float4(uo[0], uo[1], uo[2], uo[3]);
+            dn = make_float4(dd[0], dd[1], dd[2], dd[3]);
+            if (l < T - 1) {
+                qu[l][(k + 8) % NS] = un;
+                qd[l][k % ND] = dn;
             }
         }
+        const int rT = r1 - 4 * (T - 1);
+        const bool ok = own && (rT >= s0) && (rT < s1);
+        const size_t a = ok ? (size_t)rT * S + cc : junk;
+        gst4(uout + a, un);
+        gst4(dout + a, dn);
+    };
+
+    // fill: the first 8(T-1) steps produce no owned output yet
+#pragma unroll
+    for (int j = 0; j < FILL; ++j) step(j % NS, rs + j);
+    // steady march in blocks of NS steps (the last block may run past the
+    // tile; its stores go to the junk row and its loads are clamped)
+    const int nit = FILL + (s1 - s0);
+    for (int j = FILL; j < nit; j += NS) {
+#pragma unroll
+        for (int kk = 0; kk < NS; ++kk) step((FILL + kk) % NS, rs + j + kk);
+    }
+    if (R.recS >= s0 && R.recS < s1 && own) {
+#pragma unroll
+        for (int l = 0; l < T; ++l) sample_receivers(R, n + l, J0, rec[l]);
     }
 }
 
-// Sample u^{n} at the receivers only (used for the last time sample).
-__global__ void k_sample(const RunDesc *__restrict__ runs, int nruns, int n) {
+// Sample u^n (held in buffer `par`) at the receivers only (the last time sample).
+__global__ void k_sample(const RunDesc *__restrict__ runs, int nruns, int n, int par) {
     const int run = blockIdx.y;
     if (run >= nruns) return;
     const RunDesc &R = runs[run];
-    const float *u = (n & 1) ? R.u1 : R.u0;
+    const float *u = par ? R.u[1] : R.u[0];
     for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < R.nrec; r += gridDim.x * blockDim.x) {
-        const float val = u[(size_t)R.recS * R.S + R.reccol[r] + kHalo];
+        const float val = u[(size_t)R.recS * R.S + R.reccol[r] + kRing];
         const size_t o = (size_t)n * R.nrec + r;
         if (R.traces) {
             R.traces[o] = val;
@@ -577,47 +682,53 @@ struct RunSpec {
     float *traces;     // record output or NULL
 };
 
-struct Layout {
-    size_t runs_off, tiles_off, prun_off, coef_off, nodes_off, C_off, state_off, acc_off, total;
-    size_t hdr_bytes;                 // descriptors + nodes (uploaded each call)
-    std::vector<size_t> C_of_particle;   // byte offsets
-    std::vector<size_t> field_of_run;    // byte offsets of u0 (u1, dl follow)
-    std::vector<size_t> acc_of_run;
-    int ntiles;
-};
+static const int kMinBz = 20;      // smallest tile height (sizes the tile tables)
+static const int kTailBz = 40;     // tile height of the single-step launches that finish the record
 
-static int rows_per_tile_min() { return 18; }
+static int out_cols(int T) { return kTileX - 8 * T; }
 
-static size_t field_bytes(const empso_problem *p) {
-    return align_up((size_t)(p->Nz + 2 * kHalo) * p->S * sizeof(float), 256);
-}
-
-static int tiles_of(const empso_problem *p, int bz) {
+static int tiles_of(const empso_problem *p, int bz, int T) {
     const int zt = (p->Nz + bz - 1) / bz;
-    const int xt = (p->Nx + kTileX - 1) / kTileX;
+    const int xt = (p->Nx + out_cols(T) - 1) / out_cols(T);
     return zt * xt;
 }
 
-// particles: problem of each particle, and the runs (particle-major, shot-minor).
+// stored rows of a field: ring, padded grid, ring, one junk row
+static size_t field_bytes(const empso_problem *p) {
+    return align_up((size_t)(p->Nz + 2 * kRing + 1) * p->S * sizeof(float), 256);
+}
+
+struct Layout {
+    size_t runs_off, tiles_off, tiles1_off, prun_off, coef_off, nodes_off, state_off, acc_off, total;
+    size_t hdr_bytes;                      // descriptors + nodes (uploaded each call)
+    std::vector<size_t> C_of_particle;     // byte offsets
+    std::vector<size_t> field_of_run;      // byte offset of u[0] (u[1], d[0], d[1] follow)
+    std::vector<size_t> acc_of_run;
+    int ntiles, ntiles1;                   // tiles of the main depth and of single steps
+};
+
+// Workspace layout for the runs (particle-major, shot-minor); independent of
+// the tuning except for the tile counts.
 static Layout make_layout(const std::vector<const empso_problem *> &pp, const std::vector<RunSpec> &runs, int Dmax,
-                          int bz) {
+                          int bz, int T) {
     Layout L;
     const int np = (int)pp.size();
     const int nruns = (int)runs.size();
-    int ntiles_max = 0, ntiles = 0;
+    int cap = 0;
+    L.ntiles = L.ntiles1 = 0;
     for (const RunSpec &r : runs) {
-        ntiles_max += tiles_of(r.p, rows_per_tile_min());
-        ntiles += tiles_of(r.p, bz);
+        cap += tiles_of(r.p, kMinBz, kMaxT);
+        L.ntiles += tiles_of(r.p, bz, T);
+        L.ntiles1 += tiles_of(r.p, kTailBz, 1);
     }
-    L.ntiles = ntiles;
     size_t o = 0;
     L.runs_off = o; o = align_up(o + sizeof(RunDesc) * nruns, 256);
-    L.tiles_off = o; o = align_up(o + sizeof(int4) * ntiles_max, 256);
+    L.tiles_off = o; o = align_up(o + sizeof(int4) * cap, 256);
+    L.tiles1_off = o; o = align_up(o + sizeof(int4) * cap, 256);
     L.prun_off = o; o = align_up(o + sizeof(int) * (np + 1), 256);
     L.coef_off = o; o = align_up(o + sizeof(CoefDesc) * np, 256);
     L.nodes_off = o; o = align_up(o + sizeof(float) * (size_t)np * std::max(Dmax, 1), 256);
     L.hdr_bytes = o;
-    L.C_off = o;
     for (int k = 0; k < np; ++k) {
         L.C_of_particle.push_back(o);
         o += field_bytes(pp[k]);
@@ -625,7 +736,7 @@ static Layout make_layout(const std::vector<const empso_problem *> &pp, const st
     L.state_off = o;
     for (int k = 0; k < nruns; ++k) {
         L.field_of_run.push_back(o);
-        o += 3 * field_bytes(runs[k].p);
+        o += 4 * field_bytes(runs[k].p);
     }
     L.acc_off = o;
     for (int k = 0; k < nruns; ++k) {
@@ -637,12 +748,10 @@ static Layout make_layout(const std::vector<const empso_problem *> &pp, const st
 }
 
 struct Plan {
-    // key
     std::vector<const void *> key_ptrs;
     std::vector<int> key_ints;
-    // state
     Layout L;
-    std::vector<unsigned char> host_hdr;   // staging copy of the descriptor header
+    std::vector<unsigned char> host_hdr;   // host copy of the descriptor header
     unsigned char *pinned = nullptr;       // pinned staging buffer (hdr_bytes)
     hipEvent_t upload_done = nullptr;
     bool upload_pending = false;
@@ -660,47 +769,79 @@ static std::mutex g_plan_mu;
 static std::vector<Plan *> g_plans;   // small LRU
 static const size_t kMaxPlans = 8;
 
-static int launch_step(int bz, const RunDesc *runs, const int4 *tiles, int ntiles, int n, hipStream_t st) {
-    const int waves = ntiles;
-    int blocks = (waves + 3) / 4;
+static int launch_tb(int bz, int T, const RunDesc *runs, const int4 *tiles, int ntiles, int n, int par,
+                     hipStream_t st) {
+    int blocks = (ntiles + 3) / 4;
     blocks = (blocks + 7) / 8 * 8;
-    switch (bz) {
-        case 18: k_step<18><<<blocks, 256, 0, st>>>(runs, tiles, ntiles, n); break;
-        case 36: k_step<36><<<blocks, 256, 0, st>>>(runs, tiles, ntiles, n); break;
-        case 72: k_step<72><<<blocks, 256, 0, st>>>(runs, tiles, ntiles, n); break;
-        default: return EMPSO_ENOTSUP;
+#define EMPSO_TB_CASE(B, TT)                                                         \
+    if (bz == B && T == TT) {                                                        \
+        k_tb<B / kQueue, TT><<<blocks, 256, 0, st>>>(runs, tiles, ntiles, n, par);   \
+        return EMPSO_OK;                                                             \
     }
-    return EMPSO_OK;
+    EMPSO_TB_CASE(20, 1) EMPSO_TB_CASE(40, 1) EMPSO_TB_CASE(80, 1) EMPSO_TB_CASE(160, 1)
+    EMPSO_TB_CASE(20, 2) EMPSO_TB_CASE(40, 2) EMPSO_TB_CASE(80, 2) EMPSO_TB_CASE(160, 2)
+    EMPSO_TB_CASE(20, 3) EMPSO_TB_CASE(40, 3) EMPSO_TB_CASE(80, 3) EMPSO_TB_CASE(160, 3)
+#undef EMPSO_TB_CASE
+    return EMPSO_ENOTSUP;
 }
 
-// Enqueue the whole evaluation (zero state, coefficients, time loop, final
-// sample, optional reduction) on stream st.
-static int enqueue_all(const Plan &pl, unsigned char *ws, int nruns, int np, int nt, int bz, float *fitness,
-                       hipStream_t st) {
+// Enqueue the whole evaluation (zero state, coefficients, time loop in blocks
+// of T steps and single steps for the remainder, final sample, optional
+// reduction) on stream st.
+static int enqueue_all(const Plan &pl, unsigned char *ws, int nruns, int np, int nt, const empso_tuning &tu,
+                       float *fitness, hipStream_t st) {
     const Layout &L = pl.L;
     const RunDesc *runs = reinterpret_cast<const RunDesc *>(ws + L.runs_off);
     const int4 *tiles = reinterpret_cast<const int4 *>(ws + L.tiles_off);
+    const int4 *tiles1 = reinterpret_cast<const int4 *>(ws + L.tiles1_off);
     const int64_t n4 = (int64_t)(L.total - L.state_off) / 16;
     k_zero<<<2048, 256, 0, st>>>(reinterpret_cast<float4 *>(ws + L.state_off), n4);
     k_coef<<<dim3(512, np), 256, 0, st>>>(reinterpret_cast<const CoefDesc *>(ws + L.coef_off));
-    for (int n = 0; n < nt - 1; ++n) {
-        int rc = launch_step(bz, runs, tiles, L.ntiles, n, st);
+    int n = 0, par = 0;
+    while (n < nt - 1) {
+        int rc;
+        if (n + tu.tsteps <= nt - 1) {
+            rc = launch_tb(tu.bz, tu.tsteps, runs, tiles, L.ntiles, n, par, st);
+            n += tu.tsteps;
+        } else {
+            rc = launch_tb(kTailBz, 1, runs, tiles1, L.ntiles1, n, par, st);
+            n += 1;
+        }
         if (rc) return rc;
+        par ^= 1;
     }
-    k_sample<<<dim3(8, nruns), 256, 0, st>>>(runs, nruns, nt - 1);
+    k_sample<<<dim3(8, nruns), 256, 0, st>>>(runs, nruns, nt - 1, par);
     if (fitness) k_fitness<<<np, 256, 0, st>>>(runs, reinterpret_cast<const int *>(ws + L.prun_off), fitness);
     return EMPSO_OK;
+}
+
+static void fill_tiles(int4 *td, const std::vector<const empso_problem *> &pp, const std::vector<RunSpec> &runs,
+                       int bz, int T) {
+    // order: particle, z-strip, x-strip, shot (shot fastest)
+    int k = 0;
+    size_t r0 = 0;
+    const int W = out_cols(T);
+    for (size_t q = 0; q < pp.size(); ++q) {
+        const empso_problem *p = pp[q];
+        size_t r1 = r0;
+        while (r1 < runs.size() && runs[r1].particle == (int)q) ++r1;
+        const int zt = (p->Nz + bz - 1) / bz, xt = (p->Nx + W - 1) / W;
+        for (int zs = 0; zs < zt; ++zs)
+            for (int xs = 0; xs < xt; ++xs)
+                for (size_t r = r0; r < r1; ++r)
+                    td[k++] = make_int4((int)r, kRing + zs * bz, kRing + xs * W - 4 * T, 0);
+        r0 = r1;
+    }
 }
 
 // Build the host copy of the descriptor header.
 static void build_header(Plan &pl, unsigned char *ws, const std::vector<const empso_problem *> &pp,
                          const std::vector<RunSpec> &runs, const std::vector<const float *> &vp_of_particle,
-                         const double *nodes_h, int ld_nodes, int Dmax, int bz) {
+                         const double *nodes_h, int ld_nodes, int Dmax, const empso_tuning &tu) {
     const Layout &L = pl.L;
     std::vector<unsigned char> &h = pl.host_hdr;
     h.assign(L.hdr_bytes, 0);
     RunDesc *rd = reinterpret_cast<RunDesc *>(h.data() + L.runs_off);
-    int4 *td = reinterpret_cast<int4 *>(h.data() + L.tiles_off);
     int *prun = reinterpret_cast<int *>(h.data() + L.prun_off);
     CoefDesc *cd = reinterpret_cast<CoefDesc *>(h.data() + L.coef_off);
     float *nd = reinterpret_cast<float *>(h.data() + L.nodes_off);
@@ -727,35 +868,25 @@ static void build_header(Plan &pl, unsigned char *ws, const std::vector<const em
         RunDesc &d = rd[r];
         float *f = reinterpret_cast<float *>(ws + L.field_of_run[r]);
         const size_t fe = field_bytes(p) / sizeof(float);
-        d.u0 = f; d.u1 = f + fe; d.dl = f + 2 * fe;
+        d.u[0] = f; d.u[1] = f + fe; d.d[0] = f + 2 * fe; d.d[1] = f + 3 * fe;
         d.C = reinterpret_cast<const float *>(ws + L.C_of_particle[rs.particle]);
         d.obs = rs.obs; d.traces = rs.traces;
         d.acc = reinterpret_cast<double *>(ws + L.acc_of_run[r]);
         d.wav = p->d_wav; d.az = p->d_az; d.ax = p->d_ax; d.recmap = p->d_recmap; d.reccol = p->d_reccol;
         d.Nz = p->Nz; d.Nx = p->Nx; d.S = p->S; d.nrec = p->g.nrec;
-        d.recS = p->recI + kHalo;
-        d.srcS = p->srcI[rs.shot] + kHalo;
-        d.srcC = p->srcJ[rs.shot] + kHalo;
+        d.recS = p->recI + kRing;
+        d.srcS = p->srcI[rs.shot] + kRing;
+        d.srcC = p->srcJ[rs.shot] + kRing;
         d.nt = p->g.nt;
+        d.junk = p->Nz + 2 * kRing;
         d.c0 = p->c0;
         d.cz1 = p->cz[0]; d.cz2 = p->cz[1]; d.cz3 = p->cz[2]; d.cz4 = p->cz[3];
         d.cx1 = p->cx[0]; d.cx2 = p->cx[1]; d.cx3 = p->cx[2]; d.cx4 = p->cx[3];
         d.wscale = p->wscale;
     }
     while (cur < np) prun[++cur] = (int)runs.size();
-    // tiles: particle, z-strip, x-strip, shot (shot fastest)
-    int nt_ = 0;
-    size_t r0 = 0;
-    for (int k = 0; k < np; ++k) {
-        const empso_problem *p = pp[k];
-        size_t r1 = r0;
-        while (r1 < runs.size() && runs[r1].particle == k) ++r1;
-        const int zt = (p->Nz + bz - 1) / bz, xt = (p->Nx + kTileX - 1) / kTileX;
-        for (int zs = 0; zs < zt; ++zs)
-            for (int xs = 0; xs < xt; ++xs)
-                for (size_t r = r0; r < r1; ++r) td[nt_++] = make_int4((int)r, kHalo + zs * bz, kHalo + xs * kTileX, 0);
-        r0 = r1;
-    }
+    fill_tiles(reinterpret_cast<int4 *>(h.data() + L.tiles_off), pp, runs, tu.bz, tu.tsteps);
+    fill_tiles(reinterpret_cast<int4 *>(h.data() + L.tiles1_off), pp, runs, kTailBz, 1);
 }
 
 static int run_plan(Plan *pl, unsigned char *ws, int nruns, int np, int nt, const empso_tuning &tu, float *fitness,
@@ -772,7 +903,7 @@ static int run_plan(Plan *pl, unsigned char *ws, int nruns, int np, int nt, cons
     pl->upload_pending = true;
 
     if (!tu.use_graph) {
-        int rc = enqueue_all(*pl, ws, nruns, np, nt, tu.bz, fitness, st);
+        int rc = enqueue_all(*pl, ws, nruns, np, nt, tu, fitness, st);
         if (rc) EMPSO_FAIL(rc, "launch failed");
         EMPSO_HIP(hipGetLastError());
         return EMPSO_OK;
@@ -781,7 +912,7 @@ static int run_plan(Plan *pl, unsigned char *ws, int nruns, int np, int nt, cons
         if (!pl->cap_stream) EMPSO_HIP(hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking));
         hipGraph_t graph = nullptr;
         EMPSO_HIP(hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal));
-        int rc = enqueue_all(*pl, ws, nruns, np, nt, tu.bz, fitness, pl->cap_stream);
+        int rc = enqueue_all(*pl, ws, nruns, np, nt, tu, fitness, pl->cap_stream);
         hipError_t e = hipStreamEndCapture(pl->cap_stream, &graph);
         if (rc) {
             if (graph) (void)hipGraphDestroy(graph);
@@ -825,7 +956,7 @@ static Plan *find_or_make_plan(const std::vector<const void *> &kp, const std::v
 }
 
 static bool valid_tuning(const empso_tuning &t) {
-    return t.variant == 0 && (t.bz == 18 || t.bz == 36 || t.bz == 72) && t.tsteps == 1 &&
+    return (t.bz == 20 || t.bz == 40 || t.bz == 80 || t.bz == 160) && t.tsteps >= 1 && t.tsteps <= kMaxT && t.prefetch == 1 &&
            (t.use_graph == 0 || t.use_graph == 1);
 }
 
@@ -879,11 +1010,12 @@ extern "C" size_t empso_forward_workspace_bytes(const empso_problem *p, int32_t 
     std::vector<const empso_problem *> pp;
     std::vector<RunSpec> runs;
     forward_specs(p, 0, nsh, nullptr, pp, runs);
-    return make_layout(pp, runs, p->D, 18).total;
+    return make_layout(pp, runs, p->D, kMinBz, kMaxT).total;
 }
 
 extern "C" int empso_forward_shots(const empso_problem *p, const float *vp_d, int32_t shot0, int32_t nsh,
-                                   float *traces_d, void *ws, size_t ws_bytes, empso_stream stream) {
+                                   float *traces_d, void *ws, size_t ws_bytes, const empso_tuning *tuning,
+                                   empso_stream stream) {
     clear_error();
     if (!p || !vp_d || !traces_d || !ws) EMPSO_FAIL(EMPSO_EINVAL, "NULL argument");
     if (nsh < 1 || shot0 < 0 || shot0 + nsh > p->g.nshots) EMPSO_FAIL(EMPSO_EINVAL, "shot range out of bounds");
@@ -902,14 +1034,15 @@ extern "C" int empso_forward_shots(const empso_problem *p, const float *vp_d, in
     std::vector<RunSpec> runs;
     forward_specs(p, shot0, nsh, traces_d, pp, runs);
     empso_tuning tu;
-    empso_default_tuning(&tu);
+    if (tuning) tu = *tuning; else empso_default_tuning(&tu);
     tu.use_graph = 0;
+    if (!valid_tuning(tu)) EMPSO_FAIL(EMPSO_ENOTSUP, "unsupported tuning");
     std::lock_guard<std::mutex> lk(g_plan_mu);
     Plan pl;
-    pl.L = make_layout(pp, runs, p->D, tu.bz);
+    pl.L = make_layout(pp, runs, p->D, tu.bz, tu.tsteps);
     unsigned char *w = reinterpret_cast<unsigned char *>(ws);
     std::vector<const float *> vps(1, vp_d);
-    build_header(pl, w, pp, runs, vps, nullptr, 0, p->D, tu.bz);
+    build_header(pl, w, pp, runs, vps, nullptr, 0, p->D, tu);
     int rc = run_plan(&pl, w, (int)runs.size(), 1, p->g.nt, tu, nullptr, st);
     if (rc) return rc;
     // the staging buffer is freed with the local plan: wait for the upload
@@ -943,7 +1076,7 @@ extern "C" size_t empso_fitness_workspace_bytes(const empso_problem *const *prob
     std::vector<RunSpec> runs;
     int Dmax;
     if (batch_specs(probs, nprob, nullptr, pop, np, pp, runs, &Dmax)) return 0;
-    return make_layout(pp, runs, Dmax, 18).total;
+    return make_layout(pp, runs, Dmax, kMinBz, kMaxT).total;
 }
 
 extern "C" int empso_fitness_batch(const empso_problem *const *probs, int32_t nprob, const float *const *obs_d,
@@ -980,7 +1113,7 @@ extern "C" int empso_fitness_batch(const empso_problem *const *probs, int32_t np
                            p->g.vmax);
         }
     }
-    const size_t need = make_layout(pp, runs, Dmax, 18).total;
+    const size_t need = make_layout(pp, runs, Dmax, kMinBz, kMaxT).total;
     if (ws_bytes < need) EMPSO_FAIL(EMPSO_EWORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
 
     std::vector<const void *> kp;
@@ -990,14 +1123,16 @@ extern "C" int empso_fitness_batch(const empso_problem *const *probs, int32_t np
     for (int q = 0; q < nprob; ++q) kp.push_back(probs[q]);
     ki.push_back(np);
     ki.push_back(tu.bz);
+    ki.push_back(tu.tsteps);
+    ki.push_back(tu.prefetch);
     ki.push_back(tu.use_graph);
     for (int k = 0; k < np; ++k) ki.push_back(pop[k]);
 
     std::lock_guard<std::mutex> lk(g_plan_mu);
     bool fresh;
     Plan *pl = find_or_make_plan(kp, ki, &fresh);
-    if (fresh) pl->L = make_layout(pp, runs, Dmax, tu.bz);
+    if (fresh) pl->L = make_layout(pp, runs, Dmax, tu.bz, tu.tsteps);
     unsigned char *w = reinterpret_cast<unsigned char *>(ws);
-    build_header(*pl, w, pp, runs, std::vector<const float *>(), nodes_h, ld_nodes, Dmax, tu.bz);
+    build_header(*pl, w, pp, runs, std::vector<const float *>(), nodes_h, ld_nodes, Dmax, tu);
     return run_plan(pl, w, (int)runs.size(), np, pp[0]->g.nt, tu, fitness_d, (hipStream_t)stream);
 }

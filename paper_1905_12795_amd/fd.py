@@ -92,8 +92,11 @@ class Problem:
 
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h is not None and h.value:
-            lib.empso_problem_destroy(h)
+        if h is not None and h.value and lib is not None:
+            try:
+                lib.empso_problem_destroy(h)
+            except Exception:
+                pass
             self.handle = None
 
     @property
@@ -126,7 +129,7 @@ def vp_from_nodes(prob, nodes, out=None):
     return out
 
 
-def forward_shots(prob, vp, shot0=0, nsh=None, out=None, ws=None):
+def forward_shots(prob, vp, shot0=0, nsh=None, out=None, ws=None, tuning=None):
     """Traces [nsh][nt][nrec] FP32 of shots shot0.. of the model vp[nz][nx] (device FP32)."""
     _need(vp, torch.float32, (prob.info.nz, prob.info.nx), "vp")
     if nsh is None:
@@ -138,7 +141,7 @@ def forward_shots(prob, vp, shot0=0, nsh=None, out=None, ws=None):
     if ws is None:
         ws = workspace(need, vp.device)
     check(lib.empso_forward_shots(prob.handle, _ptr(vp), int(shot0), int(nsh), _ptr(out), _ptr(ws),
-                                  ws.numel(), _stream()))
+                                  ws.numel(), None if tuning is None else ctypes.byref(tuning), _stream()))
     return out
 
 

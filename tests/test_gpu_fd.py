@@ -126,9 +126,9 @@ def test_multi_tile_ragged_traces_and_fitness(gfd):
     fo, _ = ofd.fitness_batch(op, X.astype(np.float32).astype(np.float64), dobs)
     fb = gfd.FitnessBatch([gp], [torch.tensor(dobs, device="cuda")], [0] * 5)
     n2 = float(np.sum(dobs.astype(np.float64) ** 2))
-    for t in (dict(bz=18, use_graph=0), dict(bz=36, use_graph=1), dict(bz=72, use_graph=1)):
+    for t in (dict(bz=20, T=1, use_graph=0), dict(bz=40, T=2, use_graph=1), dict(bz=80, T=3, use_graph=1)):
         tu = gfd.default_tuning()
-        tu.bz, tu.use_graph = t["bz"], t["use_graph"]
+        tu.bz, tu.tsteps, tu.use_graph = t["bz"], t["T"], t["use_graph"]
         fg = fb(X, tuning=tu).cpu().numpy().astype(np.float64)
         for k in range(5):
             assert _fit_close(fg[k], fo[k], n2), (t, k, fg[k], fo[k])
@@ -142,14 +142,53 @@ def test_tiling_graph_and_repeat_are_bitwise_invariant(gfd):
     X = rng.uniform(1400, 2700, (7, 12))
     fb = gfd.FitnessBatch([gp], [dobs], [0] * 7)
     outs = []
-    for bz in (18, 36, 72):
-        for graph in (0, 1):
+    for bz in (20, 40, 80, 160):
+        for T in (1, 2, 3):
+            for graph in (0, 1):
+                tu = gfd.default_tuning()
+                tu.bz, tu.tsteps, tu.use_graph = bz, T, graph
+                for _ in range(2):
+                    outs.append(((bz, T, graph), fb(X, tuning=tu).clone()))
+    for key, o in outs[1:]:
+        assert torch.equal(o, outs[0][1]), key
+
+
+def test_wide_grid_interior_tiles_bitwise_invariant(gfd):
+    """A grid wide enough for tiles with no damping column: all tunings agree bit for bit."""
+    g = _small_geom()
+    g.update(nz=41, nx=801, tmax=0.2)
+    g["src"] = [[0.0, 4000.0]]
+    g["rec"] = [[0.0, 10.0 * j] for j in range(0, 801, 4)]
+    op, gp = _pair(gfd, g)
+    rng = np.random.default_rng(9)
+    dobs = torch.tensor(rng.standard_normal((1, gp.nt, gp.nrec)).astype(np.float32) * 1e-3, device="cuda")
+    X = rng.uniform(1400, 2700, (3, 12))
+    fb = gfd.FitnessBatch([gp], [dobs], [0] * 3)
+    ref = None
+    for bz in (20, 80, 160):
+        for T in (1, 2, 3):
             tu = gfd.default_tuning()
-            tu.bz, tu.use_graph = bz, graph
-            for _ in range(2):
-                outs.append(fb(X, tuning=tu).clone())
-    for o in outs[1:]:
-        assert torch.equal(o, outs[0])
+            tu.bz, tu.tsteps = bz, T
+            got = fb(X, tuning=tu).clone()
+            if ref is None:
+                ref = got
+            assert torch.equal(got, ref), (bz, T)
+
+
+def test_temporal_blocking_traces_bitwise_equal_single_step(gfd):
+    """Record mode through the same kernels: traces at every sample are identical."""
+    g = _small_geom()
+    op, gp = _pair(gfd, g)
+    rng = np.random.default_rng(8)
+    vp = torch.tensor(ofd.vp_from_nodes(rng.uniform(1500, 2600, 12), 3, 4, g["nz"], g["nx"]),
+                      dtype=torch.float32, device="cuda")
+    ref = gfd.forward_shots(gp, vp).cpu()
+    assert torch.isfinite(ref).all() and ref.abs().max() > 0
+    for T in (2, 3):
+        tu = gfd.default_tuning()
+        tu.tsteps = T
+        got = gfd.forward_shots(gp, vp, tuning=tu).cpu()
+        assert torch.equal(got, ref), T
 
 
 def test_mixed_sizes_in_one_batch_equal_separate_batches(gfd):
