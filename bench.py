@@ -25,9 +25,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-BYTES_PER_UPDATE = 16          # read u^n, read delta, write u^{n+1}, write delta
+# Algorithmic HBM bytes per grid-point update of the scheme: read u^n and
+# delta^n, write u^{n+1} and delta^{n+1} (FP32). The coefficient field is
+# shared by the 16 shots of a particle and excluded. A launch that advances T
+# time steps performs T updates per point.
+BYTES_PER_UPDATE = 16
 METRIC = "fitness evals/s and Gpt-updates/s on 1 MI355X; % HBM peak; surrogate vs plain"
-STEP_KERNEL = "k_step"
 
 
 def kernel_source_hash():
@@ -37,16 +40,18 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(per_launch_updates):
+def measured_traffic(per_launch_updates, tu):
     """HBM bytes per stencil launch from the committed counter summary, if it
-    was taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "k_step_realistic_traffic.json")
+    was taken on the current kernel source with this tuning; else None."""
+    path = os.path.join(ROOT, "profiles", "k_tb_realistic_traffic.json")
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
     if d.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
     if d.get("updates_per_launch") != per_launch_updates:
+        return None
+    if d.get("tuning", {}).get("bz") != tu.bz or d.get("tuning", {}).get("tsteps") != tu.tsteps:
         return None
     return d.get("hbm_bytes_per_launch")
 
@@ -88,9 +93,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=2000)
-    ap.add_argument("--bz", type=int, default=None)
-    ap.add_argument("--copy-probe-mib", type=int, default=0,
-                    help="first run one device-to-device copy of this many MiB (counter calibration)")
+    ap.add_argument("--bz", type=int, default=None, help="fix the tile height (default: autotune)")
+    ap.add_argument("--tsteps", type=int, default=None, help="fix the temporal-blocking depth")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -104,32 +108,27 @@ def main():
     from workloads.configs import config, true_model
 
     dev = "cuda"
-    if args.copy_probe_mib:
-        n = args.copy_probe_mib * (1 << 20) // 4
-        src = torch.ones(n, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        dst.copy_(src)
-        e1.record()
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n,
-                          "copy_probe_GBps": 8 * n / (e0.elapsed_time(e1) * 1e-3) / 1e9}),
-              file=sys.stderr, flush=True)
-        del src, dst
     g = config("realistic")
     prob = fd.Problem(g)
     vp = torch.tensor(true_model(g), dtype=torch.float32, device=dev)
     dobs = fd.forward_shots(prob, vp)
     swarm = EMPSO(g["node_lo"], g["node_hi"], g["particles"], gen=10, seed=g["particle_seed"])
-    tu = fd.default_tuning()
-    if args.bz:
-        tu.bz = args.bz
-    fb = fd.FitnessBatch([prob], [dobs], [0] * g["particles"], tuning=tu)
+    fb = fd.FitnessBatch([prob], [dobs], [0] * g["particles"])
+    if args.bz or args.tsteps:
+        tu = fd.default_tuning()
+        tu.bz = args.bz or tu.bz
+        tu.tsteps = args.tsteps or tu.tsteps
+        fb.tuning = tu
+        tuned = None
+    else:
+        tuned = fb.autotune(swarm.ask())      # setup, untimed
+        tu = fb.tuning
+    T = tu.tsteps
     nsteps = prob.nt - 1
-    upd_per_step = fb.updates
-    upd_per_launch = upd_per_step // nsteps
+    n_main, n_tail = nsteps // T, nsteps % T
+    points = fb.updates // nsteps             # grid points of all runs (one update each per time step)
+    upd_per_step = fb.updates                 # one step = one fitness call = all time steps of all runs
+    upd_per_launch = points * T
 
     def step():
         f = fb(swarm.ask())
@@ -153,12 +152,16 @@ def main():
     ms_step = 1000.0 * wall / args.steps
     evals_per_s = g["particles"] * args.steps / wall
     gpt = upd_per_step * args.steps / wall / 1e9
-    # dominant kernel: the per-step stencil launch; its average duration is
-    # bounded above by the fitness call's event time divided by the launches
-    launch_s = (np.mean(gpu_ms) / 1000.0) / nsteps
+    # Dominant kernel: the T-step launch. The fitness call is one graph on the
+    # current stream: the events around it bound its launches' average
+    # duration from above (the call also holds a few tiny kernels and
+    # (nt-1) mod T single-step launches, counted as 1/T of a launch each).
+    launch_s = (np.mean(gpu_ms) / 1000.0) / (n_main + n_tail / T)
+    # isolated timing of the same kernel (HIP events on the launch stream)
+    iso_us_step = fb.time_tuning(swarm.ask(), tu, reps=8)
     alg = upd_per_launch * BYTES_PER_UPDATE
     achieved = alg / launch_s / 1e9
-    traffic = measured_traffic(upd_per_launch)
+    traffic = measured_traffic(upd_per_launch, tu)
     out = {
         "metric": METRIC, "value": evals_per_s, "unit": "fitness evals/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
@@ -168,14 +171,17 @@ def main():
                                "shots (512 runs), 461 receivers, 5 Hz Ricker, 3 s (nt %d), 5x12 nodes, "
                                "one EMPSO iteration per step" % prob.nt,
                    "runs_per_step": g["particles"] * prob.nshots, "nt": prob.nt,
-                   "tuning": tu.as_dict()},
+                   "tuning": tu.as_dict(), "autotuned": tuned is not None},
         "gpt_updates_per_s": gpt,
         "fitness_call_ms": float(np.mean(gpu_ms)),
         "best_fitness": float(swarm.fg),
-        "roofline": {"bound": "hbm", "kernel": STEP_KERNEL, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+        "roofline": {"bound": "hbm", "kernel": "k_tb<%d,%d>" % (tu.bz // 10, T), "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic,
                      "algorithmic_bytes_per_launch": alg, "updates_per_launch": upd_per_launch,
-                     "avg_launch_us": launch_s * 1e6},
+                     "bytes_per_update": BYTES_PER_UPDATE, "time_steps_per_launch": T,
+                     "avg_launch_us": launch_s * 1e6, "isolated_launch_us": iso_us_step * T,
+                     "measured_frac": None if traffic is None else traffic / launch_s / 1e9 / HBM_PEAK_GBS},
     }
     if not args.no_cpu_baseline:
         threads = min(16, os.cpu_count() or 1)

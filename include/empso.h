@@ -187,6 +187,27 @@ int empso_fitness_batch(const empso_problem *const *probs, int32_t nprob,
 /* Default tuning used when NULL is passed. */
 int empso_default_tuning(empso_tuning *out);
 
+/* Autotuner: with the same arguments as empso_fitness_batch, time a few
+ * launches of the finite-difference kernel for every supported tile height
+ * and temporal-blocking depth on this batch and write the fastest tuning to
+ * *best (graph replay on) and its time per time step in microseconds to
+ * *best_us_per_step (may be NULL). Every tuning gives bit-identical results.
+ * Synchronises the stream; overwrites the workspace. */
+int empso_autotune_fitness(const empso_problem *const *probs, int32_t nprob, const float *const *obs_d,
+                           const int32_t *prob_of_particle, int32_t np, const double *nodes_h, int32_t ld_nodes,
+                           void *ws, size_t ws_bytes, empso_tuning *best, float *best_us_per_step,
+                           empso_stream stream);
+
+/* Time one tuning the way the autotuner does: set the batch up, run one
+ * untimed and `reps` timed launches of the finite-difference kernel from time
+ * 0, and write the time per time step in microseconds. Used for tuning and
+ * for hardware-counter collection on a few launches. Synchronises the
+ * stream; overwrites the workspace. */
+int empso_time_tuning(const empso_problem *const *probs, int32_t nprob, const float *const *obs_d,
+                      const int32_t *prob_of_particle, int32_t np, const double *nodes_h, int32_t ld_nodes,
+                      void *ws, size_t ws_bytes, const empso_tuning *tuning, int32_t reps, float *us_per_step,
+                      empso_stream stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -68,6 +68,12 @@ SIGNATURES = {
                                            ctypes.c_int32, _P(ctypes.c_double), ctypes.c_int32, _vp,
                                            _vp, ctypes.c_size_t, _P(Tuning), _vp]),
     "empso_default_tuning": (ctypes.c_int, [_P(Tuning)]),
+    "empso_autotune_fitness": (ctypes.c_int, [_P(_vp), ctypes.c_int32, _P(_vp), _P(ctypes.c_int32),
+                                              ctypes.c_int32, _P(ctypes.c_double), ctypes.c_int32, _vp,
+                                              ctypes.c_size_t, _P(Tuning), _P(ctypes.c_float), _vp]),
+    "empso_time_tuning": (ctypes.c_int, [_P(_vp), ctypes.c_int32, _P(_vp), _P(ctypes.c_int32),
+                                         ctypes.c_int32, _P(ctypes.c_double), ctypes.c_int32, _vp,
+                                         ctypes.c_size_t, _P(Tuning), ctypes.c_int32, _P(ctypes.c_float), _vp]),
 }
 
 

@@ -273,8 +273,8 @@ extern "C" int empso_problem_get_info(const empso_problem *p, empso_problem_info
 extern "C" int empso_default_tuning(empso_tuning *t) {
     if (!t) EMPSO_FAIL(EMPSO_EINVAL, "NULL argument");
     t->variant = 0;
-    t->bz = 40;
-    t->tsteps = 1;
+    t->bz = 160;
+    t->tsteps = 3;
     t->prefetch = 1;
     t->use_graph = 1;
     return EMPSO_OK;
@@ -292,7 +292,7 @@ struct RunDesc {
     const float *wav, *az, *ax;
     const int *recmap, *reccol;
     int Nz, Nx, S, nrec, recS, srcS, srcC, nt;
-    int junk;                   // stored row that absorbs discarded stores (never read)
+    unsigned fbytes;            // bytes of one stored field (u, delta or C)
     float c0, cz1, cz2, cz3, cz4, cx1, cx2, cx3, cx4, wscale;
 };
 
@@ -380,16 +380,25 @@ template <typename T>
 __device__ __forceinline__ T sld(const T *p) { return *(const __attribute__((address_space(4))) T *)p; }
 
 typedef float v4f __attribute__((ext_vector_type(4)));
-typedef __attribute__((address_space(1))) const v4f gcv4f;
-typedef __attribute__((address_space(1))) v4f gv4f;
-__device__ __forceinline__ float4 gld4(const float *p) {
-    const v4f v = *(gcv4f *)p;
+
+// Raw buffer accesses (MUBUF) with hardware range checking: a load whose byte
+// offset lies outside [0, num_records) returns zero and such a store is
+// dropped. Offsets are 32-bit, so rows above the field (negative offsets)
+// are outside too. kDrop is an offset that is always outside.
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+static constexpr int kDrop = (int)0x80000000u;
+__device__ __forceinline__ rsrc_t make_rsrc(const float *base, unsigned bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(base), (short)0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ float4 bld4(rsrc_t r, int off) {
+    const v4f v = __builtin_bit_cast(v4f, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
     return make_float4(v.x, v.y, v.z, v.w);
 }
-__device__ __forceinline__ void gst4(float *p, float4 v) {
+__device__ __forceinline__ void bst4(rsrc_t r, int off, float4 v) {
     v4f w;
     w.x = v.x; w.y = v.y; w.z = v.z; w.w = v.w;
-    *(gv4f *)p = w;
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(v4u, w), r, off, 0, 0);
 }
 
 // Accumulate (or record) the receiver samples held by one lane: u4 are the
@@ -434,7 +443,9 @@ __device__ __forceinline__ float from_lane_above(float v) {
 // updates row r - 4(t-1) from the 9-row queue of level t-1's results and the
 // delta that level t-1 produced for that row 4 steps earlier (a 5-slot queue).
 // Level T writes u^{n+T} and delta^{n+T} for owned rows and columns; every
-// other store is sent to the junk row, so the loop body has no branches.
+// other store gets an out-of-range buffer offset and is dropped by the
+// hardware, so the loop body has no branches. Rows above or below the stored
+// field read as zero for the same reason.
 // Points outside the padded grid are forced to zero at every level.
 // Receiver samples of each level (u^{n+t-1} on the receiver row) are kept in
 // registers and accumulated after the march by the owning lanes.
@@ -444,7 +455,7 @@ __global__ __launch_bounds__(256) void k_tb(const RunDesc *__restrict__ runs, co
     constexpr int NS = kQueue;
     constexpr int ND = 5;
     constexpr int BZ = M * NS;
-    constexpr int FILL = 8 * (T - 1);
+    constexpr int FILL = 8 * (T - 1);               // march steps before the first owned row
     constexpr int TQ = T > 1 ? T - 1 : 1;
     const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
     const int tix = __builtin_amdgcn_readfirstlane(lb * 4 + (int)(threadIdx.x >> 6));
@@ -453,21 +464,21 @@ __global__ __launch_bounds__(256) void k_tb(const RunDesc *__restrict__ runs, co
     const int4 t = tiles[tix];
     const RunDesc R = runs[t.x];
     const int S = R.S;
-    const int top = kRing, bot = R.Nz + kRing;      // stored rows of the padded grid
-    const int rmax = R.Nz + 2 * kRing - 1;          // last readable stored row
+    const int bot = R.Nz + kRing;                   // end of the stored rows of the padded grid
     // (selects, not R.u[par]: a runtime index would move R to scratch memory)
-    const float *uin = par ? R.u[1] : R.u[0];
-    const float *din = par ? R.d[1] : R.d[0];
-    float *uout = par ? R.u[0] : R.u[1];
-    float *dout = par ? R.d[0] : R.d[1];
-    const float *Cf = R.C;
+    const rsrc_t uin = make_rsrc(par ? R.u[1] : R.u[0], R.fbytes);
+    const rsrc_t din = make_rsrc(par ? R.d[1] : R.d[0], R.fbytes);
+    const rsrc_t uout = make_rsrc(par ? R.u[0] : R.u[1], R.fbytes);
+    const rsrc_t dout = make_rsrc(par ? R.d[0] : R.d[1], R.fbytes);
+    const rsrc_t Cf = make_rsrc(R.C, R.fbytes);
     const int c = t.z + 4 * lane;                   // stored column of this lane's first element
     const int cc = min(c, S - 4);                   // past the row: its zero tail
     const int J0 = c - kRing;
     const bool own = (lane >= T) && (lane < 64 - T);
     const int s0 = t.y;
     const int s1 = min(s0 + BZ, bot);
-    const size_t junk = (size_t)R.junk * S + cc;
+    const int lcol = 4 * cc;                        // byte offset of the lane's columns in a row
+    const int rowb = 4 * S;                         // bytes per stored row
 
     float axk[4];
     bool inx[4];
@@ -487,11 +498,11 @@ __global__ __launch_bounds__(256) void k_tb(const RunDesc *__restrict__ runs, co
     const int rs = s0 - 4 * (T - 1);                // level-1 row of the first march step
     float4 q0[NS], qu[TQ][NS], qd[TQ][ND], dq[2], cq[T][2], rec[T];
 #pragma unroll
-    for (int j = 0; j < 9; ++j) q0[j] = gld4(uin + (size_t)min(rs - 4 + j, rmax) * S + cc);
-    dq[0] = gld4(din + (size_t)min(rs, rmax) * S + cc);
+    for (int j = 0; j < 9; ++j) q0[j] = bld4(uin, (rs - 4 + j) * rowb + lcol);
+    dq[0] = bld4(din, rs * rowb + lcol);
 #pragma unroll
     for (int l = 0; l < T; ++l) {
-        cq[l][0] = gld4(Cf + (size_t)min(max(rs - 4 * l, 0), rmax) * S + cc);
+        cq[l][0] = bld4(Cf, (rs - 4 * l) * rowb + lcol);
         rec[l] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
     // the level queues fill during the first march steps; start them at zero
@@ -505,11 +516,10 @@ __global__ __launch_bounds__(256) void k_tb(const RunDesc *__restrict__ runs, co
 
     // One march step: k = (step index) mod 10, known at compile time.
     auto step = [&](const int k, const int r1) {
-        q0[(k + 9) % NS] = gld4(uin + (size_t)min(r1 + 5, rmax) * S + cc);
-        dq[(k + 1) & 1] = gld4(din + (size_t)min(r1 + 1, rmax) * S + cc);
+        q0[(k + 9) % NS] = bld4(uin, (r1 + 5) * rowb + lcol);
+        dq[(k + 1) & 1] = bld4(din, (r1 + 1) * rowb + lcol);
 #pragma unroll
-        for (int l = 0; l < T; ++l)
-            cq[l][(k + 1) & 1] = gld4(Cf + (size_t)min(max(r1 + 1 - 4 * l, 0), rmax) * S + cc);
+        for (int l = 0; l < T; ++l) cq[l][(k + 1) & 1] = bld4(Cf, (r1 + 1 - 4 * l) * rowb + lcol);
         float4 un = make_float4(0.f, 0.f, 0.f, 0.f), dn = un;
 #pragma unroll
         for (int l = 0; l < T; ++l) {
@@ -522,7 +532,7 @@ __global__ __launch_bounds__(256) void k_tb(const RunDesc *__restrict__ runs, co
             const float4 d4 = (l == 0) ? dq[k & 1] : qd[l > 0 ? l - 1 : 0][(k + 1) % ND];
             const float4 C4 = cq[l][k & 1];
             const int r = r1 - 4 * l;
-            const bool rowin = (r >= top) && (r < bot);
+            const bool rowin = (r >= kRing) && (r < bot);
             const float v[12] = {from_lane_below(ce.x), from_lane_below(ce.y),
                                  from_lane_below(ce.z), from_lane_below(ce.w),
                                  ce.x, ce.y, ce.z, ce.w,
@@ -534,25 +544,28 @@ __global__ __launch_bounds__(256) void k_tb(const RunDesc *__restrict__ runs, co
             const float pz4[4] = {p4.x, p4.y, p4.z, p4.w}, mz4[4] = {m4.x, m4.y, m4.z, m4.w};
             const float dv[4] = {d4.x, d4.y, d4.z, d4.w};
             const float Cv[4] = {C4.x, C4.y, C4.z, C4.w};
-            const float azr = sld(R.az + min(max(r - top, 0), R.Nz - 1));
+            const float azr = sld(R.az + min(max(r - kRing, 0), R.Nz - 1));
             const bool damped = tile_xdamp || (azr != 0.0f);
             const bool srow = (r == R.srcS);
             float uo[4], dd[4];
 #pragma unroll
             for (int k2 = 0; k2 < 4; ++k2) {
                 const float u = v[4 + k2];
-                float lap = R.c0 * u;
-                lap = fmaf(R.cz1, pz1[k2] + mz1[k2], lap);
-                lap = fmaf(R.cz2, pz2[k2] + mz2[k2], lap);
-                lap = fmaf(R.cz3, pz3[k2] + mz3[k2], lap);
-                lap = fmaf(R.cz4, pz4[k2] + mz4[k2], lap);
-                lap = fmaf(R.cx1, v[3 + k2] + v[5 + k2], lap);
-                lap = fmaf(R.cx2, v[2 + k2] + v[6 + k2], lap);
-                lap = fmaf(R.cx3, v[1 + k2] + v[7 + k2], lap);
-                lap = fmaf(R.cx4, v[0 + k2] + v[8 + k2], lap);
+                // Laplacian as a sum of small terms c_k ((u_{+k} + u_{-k}) - 2u),
+                // farthest neighbours first: the centre weight is never formed,
+                // so no large partial sum cancels (FP32 accuracy over long runs).
+                const float u2 = u + u;
+                float lap = R.cz4 * ((pz4[k2] + mz4[k2]) - u2);
+                lap = fmaf(R.cz3, (pz3[k2] + mz3[k2]) - u2, lap);
+                lap = fmaf(R.cz2, (pz2[k2] + mz2[k2]) - u2, lap);
+                lap = fmaf(R.cz1, (pz1[k2] + mz1[k2]) - u2, lap);
+                lap = fmaf(R.cx4, (v[0 + k2] + v[8 + k2]) - u2, lap);
+                lap = fmaf(R.cx3, (v[1 + k2] + v[7 + k2]) - u2, lap);
+                lap = fmaf(R.cx2, (v[2 + k2] + v[6 + k2]) - u2, lap);
+                lap = fmaf(R.cx1, (v[3 + k2] + v[5 + k2]) - u2, lap);
                 lap += (srow && (c + k2 == R.srcC)) ? fsrc[l] : 0.0f;
-                // The damped form reduces bit for bit to the undamped one when
-                // a = 0 ((1-a) dv = dv, rcp(1) = 1), so the result of a point
+                // The damped form reduces bit for bit to the undamped one
+                // when a = 0 ((1-a) dv = dv, rcp(1) = 1), so a point's result
                 // does not depend on which branch its tile takes.
                 float d;
                 if (damped) {
@@ -576,16 +589,16 @@ __global__ __launch_bounds__(256) void k_tb(const RunDesc *__restrict__ runs, co
         }
         const int rT = r1 - 4 * (T - 1);
         const bool ok = own && (rT >= s0) && (rT < s1);
-        const size_t a = ok ? (size_t)rT * S + cc : junk;
-        gst4(uout + a, un);
-        gst4(dout + a, dn);
+        const int a = ok ? rT * rowb + lcol : kDrop;   // dropped by the range check
+        bst4(uout, a, un);
+        bst4(dout, a, dn);
     };
 
     // fill: the first 8(T-1) steps produce no owned output yet
 #pragma unroll
     for (int j = 0; j < FILL; ++j) step(j % NS, rs + j);
     // steady march in blocks of NS steps (the last block may run past the
-    // tile; its stores go to the junk row and its loads are clamped)
+    // tile; those stores are dropped)
     const int nit = FILL + (s1 - s0);
     for (int j = FILL; j < nit; j += NS) {
 #pragma unroll
@@ -693,9 +706,9 @@ static int tiles_of(const empso_problem *p, int bz, int T) {
     return zt * xt;
 }
 
-// stored rows of a field: ring, padded grid, ring, one junk row
+// stored rows of a field: ring, padded grid, ring
 static size_t field_bytes(const empso_problem *p) {
-    return align_up((size_t)(p->Nz + 2 * kRing + 1) * p->S * sizeof(float), 256);
+    return align_up((size_t)(p->Nz + 2 * kRing) * p->S * sizeof(float), 256);
 }
 
 struct Layout {
@@ -878,7 +891,7 @@ static void build_header(Plan &pl, unsigned char *ws, const std::vector<const em
         d.srcS = p->srcI[rs.shot] + kRing;
         d.srcC = p->srcJ[rs.shot] + kRing;
         d.nt = p->g.nt;
-        d.junk = p->Nz + 2 * kRing;
+        d.fbytes = (unsigned)field_bytes(p);
         d.c0 = p->c0;
         d.cz1 = p->cz[0]; d.cz2 = p->cz[1]; d.cz3 = p->cz[2]; d.cz4 = p->cz[3];
         d.cx1 = p->cx[0]; d.cx2 = p->cx[1]; d.cx3 = p->cx[2]; d.cx4 = p->cx[3];
@@ -1135,4 +1148,133 @@ extern "C" int empso_fitness_batch(const empso_problem *const *probs, int32_t np
     unsigned char *w = reinterpret_cast<unsigned char *>(ws);
     build_header(*pl, w, pp, runs, std::vector<const float *>(), nodes_h, ld_nodes, Dmax, tu);
     return run_plan(pl, w, (int)runs.size(), np, pp[0]->g.nt, tu, fitness_d, (hipStream_t)stream);
+}
+
+// ---------------------------------------------------------------------------
+// Timing of one tuning and the autotuner built on it. Every valid tuning gives
+// identical results, so the choice only affects speed.
+// ---------------------------------------------------------------------------
+static int batch_prepare(const empso_problem *const *probs, int32_t nprob, const float *const *obs_d,
+                         const int32_t *pop, int32_t np, const double *nodes_h, int32_t ld_nodes, void *ws,
+                         size_t ws_bytes, std::vector<const empso_problem *> &pp, std::vector<RunSpec> &runs,
+                         int *Dmax) {
+    if (!probs || !obs_d || !pop || !nodes_h || !ws) EMPSO_FAIL(EMPSO_EINVAL, "NULL argument");
+    if (nprob < 1 || np < 1) EMPSO_FAIL(EMPSO_EINVAL, "nprob and np must be >= 1");
+    if (reinterpret_cast<uintptr_t>(ws) % 256) EMPSO_FAIL(EMPSO_EINVAL, "workspace must be 256-byte aligned");
+    for (int q = 0; q < nprob; ++q) {
+        if (!probs[q] || !obs_d[q]) EMPSO_FAIL(EMPSO_EINVAL, "probs[%d] or obs_d[%d] is NULL", q, q);
+        if (probs[q]->g.nt != probs[0]->g.nt) EMPSO_FAIL(EMPSO_ENOTSUP, "all problems of a batch must share nt");
+    }
+    int rc = batch_specs(probs, nprob, obs_d, pop, np, pp, runs, Dmax);
+    if (rc) return rc;
+    if (ld_nodes < *Dmax) EMPSO_FAIL(EMPSO_EINVAL, "ld_nodes = %d < %d", ld_nodes, *Dmax);
+    for (int k = 0; k < np; ++k)
+        for (int d = 0; d < pp[k]->D; ++d) {
+            const double v = nodes_h[(size_t)k * ld_nodes + d];
+            if (!(v >= pp[k]->g.vmin && v <= pp[k]->g.vmax))
+                EMPSO_FAIL(EMPSO_ERANGE, "node %d of particle %d = %g outside [%g, %g]", d, k, v, pp[k]->g.vmin,
+                           pp[k]->g.vmax);
+        }
+    if (ws_bytes < make_layout(pp, runs, *Dmax, kMinBz, kMaxT).total)
+        EMPSO_FAIL(EMPSO_EWORKSPACE, "workspace too small");
+    return EMPSO_OK;
+}
+
+// Set up the batch for tuning tu (header, zero state, coefficients), run
+// `warm` untimed and `reps` timed launches of depth tu.tsteps from time 0.
+static int time_one(const std::vector<const empso_problem *> &pp, const std::vector<RunSpec> &runs, int Dmax,
+                    const double *nodes_h, int ld_nodes, unsigned char *w, const empso_tuning &tu, int warm, int reps,
+                    hipEvent_t e0, hipEvent_t e1, hipStream_t st, float *us_per_step) {
+    Plan pl;
+    pl.L = make_layout(pp, runs, Dmax, tu.bz, tu.tsteps);
+    build_header(pl, w, pp, runs, std::vector<const float *>(), nodes_h, ld_nodes, Dmax, tu);
+    const Layout &L = pl.L;
+    EMPSO_HIP(hipMemcpyAsync(w, pl.host_hdr.data(), L.hdr_bytes, hipMemcpyHostToDevice, st));
+    EMPSO_HIP(hipStreamSynchronize(st));
+    const RunDesc *rd = reinterpret_cast<const RunDesc *>(w + L.runs_off);
+    const int4 *td = reinterpret_cast<const int4 *>(w + L.tiles_off);
+    k_zero<<<2048, 256, 0, st>>>(reinterpret_cast<float4 *>(w + L.state_off), (int64_t)(L.total - L.state_off) / 16);
+    k_coef<<<dim3(512, (int)pp.size()), 256, 0, st>>>(reinterpret_cast<const CoefDesc *>(w + L.coef_off));
+    for (int r = 0; r < warm; ++r)
+        if (launch_tb(tu.bz, tu.tsteps, rd, td, L.ntiles, 0, 0, st)) EMPSO_FAIL(EMPSO_ENOTSUP, "bad tuning");
+    EMPSO_HIP(hipEventRecord(e0, st));
+    for (int r = 0; r < reps; ++r)
+        if (launch_tb(tu.bz, tu.tsteps, rd, td, L.ntiles, 0, 0, st)) EMPSO_FAIL(EMPSO_ENOTSUP, "bad tuning");
+    EMPSO_HIP(hipEventRecord(e1, st));
+    EMPSO_HIP(hipEventSynchronize(e1));
+    EMPSO_HIP(hipGetLastError());
+    float ms = 0.f;
+    EMPSO_HIP(hipEventElapsedTime(&ms, e0, e1));
+    *us_per_step = 1000.f * ms / (reps * tu.tsteps);
+    return EMPSO_OK;
+}
+
+extern "C" int empso_time_tuning(const empso_problem *const *probs, int32_t nprob, const float *const *obs_d,
+                                 const int32_t *pop, int32_t np, const double *nodes_h, int32_t ld_nodes, void *ws,
+                                 size_t ws_bytes, const empso_tuning *tuning, int32_t reps, float *us_per_step,
+                                 empso_stream stream) {
+    clear_error();
+    if (!tuning || !us_per_step) EMPSO_FAIL(EMPSO_EINVAL, "NULL argument");
+    if (reps < 1) EMPSO_FAIL(EMPSO_EINVAL, "reps must be >= 1");
+    empso_tuning tu = *tuning;
+    tu.use_graph = 0;
+    if (!valid_tuning(tu)) EMPSO_FAIL(EMPSO_ENOTSUP, "unsupported tuning");
+    std::vector<const empso_problem *> pp;
+    std::vector<RunSpec> runs;
+    int Dmax;
+    int rc = batch_prepare(probs, nprob, obs_d, pop, np, nodes_h, ld_nodes, ws, ws_bytes, pp, runs, &Dmax);
+    if (rc) return rc;
+    hipEvent_t e0, e1;
+    EMPSO_HIP(hipEventCreate(&e0));
+    EMPSO_HIP(hipEventCreate(&e1));
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    rc = time_one(pp, runs, Dmax, nodes_h, ld_nodes, reinterpret_cast<unsigned char *>(ws), tu, 1, reps, e0, e1,
+                  (hipStream_t)stream, us_per_step);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
+}
+
+extern "C" int empso_autotune_fitness(const empso_problem *const *probs, int32_t nprob, const float *const *obs_d,
+                                      const int32_t *pop, int32_t np, const double *nodes_h, int32_t ld_nodes,
+                                      void *ws, size_t ws_bytes, empso_tuning *best, float *best_us_per_step,
+                                      empso_stream stream) {
+    clear_error();
+    if (!best) EMPSO_FAIL(EMPSO_EINVAL, "NULL argument");
+    std::vector<const empso_problem *> pp;
+    std::vector<RunSpec> runs;
+    int Dmax;
+    int rc = batch_prepare(probs, nprob, obs_d, pop, np, nodes_h, ld_nodes, ws, ws_bytes, pp, runs, &Dmax);
+    if (rc) return rc;
+    hipEvent_t e0, e1;
+    EMPSO_HIP(hipEventCreate(&e0));
+    EMPSO_HIP(hipEventCreate(&e1));
+    const int bzs[4] = {20, 40, 80, 160};
+    float best_us = 1e30f;
+    empso_tuning bt;
+    empso_default_tuning(&bt);
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    for (int T = 1; T <= kMaxT && rc == EMPSO_OK; ++T) {
+        for (int bi = 0; bi < 4 && rc == EMPSO_OK; ++bi) {
+            empso_tuning tu;
+            empso_default_tuning(&tu);
+            tu.bz = bzs[bi];
+            tu.tsteps = T;
+            tu.use_graph = 0;
+            float us = 0.f;
+            rc = time_one(pp, runs, Dmax, nodes_h, ld_nodes, reinterpret_cast<unsigned char *>(ws), tu, 2, 4, e0, e1,
+                          (hipStream_t)stream, &us);
+            if (rc == EMPSO_OK && us < best_us) {
+                best_us = us;
+                bt = tu;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    bt.use_graph = 1;
+    *best = bt;
+    if (best_us_per_step) *best_us_per_step = best_us;
+    return EMPSO_OK;
 }

@@ -190,6 +190,33 @@ class FitnessBatch:
     def updates(self):
         return sum(self.probs[q].updates_per_run * self.probs[q].nshots for q in self.pop)
 
+    def autotune(self, nodes):
+        """Pick the fastest tile height / temporal-blocking depth for this batch
+        (library autotuner) and keep it. Returns (tuning dict, us per time step)."""
+        x = np.ascontiguousarray(np.asarray(nodes, dtype=np.float64))
+        if x.shape != (self.np, self.Dmax):
+            raise ValueError("nodes must be [%d][%d]" % (self.np, self.Dmax))
+        best = Tuning()
+        us = ctypes.c_float()
+        check(lib.empso_autotune_fitness(self._ph, len(self.probs), self._oh, self._pop_ptr(), self.np,
+                                         x.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), self.Dmax,
+                                         _ptr(self.ws), self.ws.numel(), ctypes.byref(best), ctypes.byref(us),
+                                         _stream()))
+        self.tuning = best
+        return best.as_dict(), float(us.value)
+
+    def time_tuning(self, nodes, tuning, reps=4):
+        """Microseconds per time step of one tuning over `reps` kernel launches."""
+        x = np.ascontiguousarray(np.asarray(nodes, dtype=np.float64))
+        if x.shape != (self.np, self.Dmax):
+            raise ValueError("nodes must be [%d][%d]" % (self.np, self.Dmax))
+        us = ctypes.c_float()
+        check(lib.empso_time_tuning(self._ph, len(self.probs), self._oh, self._pop_ptr(), self.np,
+                                    x.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), self.Dmax,
+                                    _ptr(self.ws), self.ws.numel(), ctypes.byref(tuning), int(reps),
+                                    ctypes.byref(us), _stream()))
+        return float(us.value)
+
     def __call__(self, nodes, tuning=None):
         """nodes: host float64 [np][D] (row stride Dmax). Returns the device fitness tensor."""
         x = np.ascontiguousarray(np.asarray(nodes, dtype=np.float64))

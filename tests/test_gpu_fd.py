@@ -230,3 +230,18 @@ def test_error_paths(gfd):
     with pytest.raises(EmpsoError) as ei:
         gfd.forward_shots(gp, vp)
     assert ei.value.status == -3
+
+
+def test_autotuner_picks_a_valid_tuning_with_identical_results(gfd):
+    g = _small_geom()
+    op, gp = _pair(gfd, g)
+    rng = np.random.default_rng(10)
+    dobs = torch.tensor(rng.standard_normal((3, gp.nt, gp.nrec)).astype(np.float32) * 1e-3, device="cuda")
+    X = rng.uniform(1400, 2700, (4, 12))
+    fb = gfd.FitnessBatch([gp], [dobs], [0] * 4)
+    ref = fb(X).clone()
+    best, us = fb.autotune(X)
+    assert best["bz"] in (20, 40, 80, 160) and 1 <= best["tsteps"] <= 3 and best["use_graph"] == 1
+    assert us > 0
+    assert fb.time_tuning(X, fb.tuning, reps=2) > 0
+    assert torch.equal(fb(X), ref)

@@ -1,0 +1,111 @@
+"""Parity at the benchmark's full sizes and launch configuration (run on an MI355X).
+
+The oracle computes sampled outputs one by one: the observed data of every
+shot, the traces of two shots, and the fitness of a few particles. The GPU
+evaluates the whole batch exactly as bench.py does (autotuned tuning, HIP
+graph). Bar: 2e-4 relative L2 for traces, the same bar for misfits (or its
+square-root form near the optimum).
+"""
+import copy
+import sys
+import time
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import fd as ofd
+from workloads.configs import config, true_model
+from workloads.models import uniform_particles
+
+pytestmark = pytest.mark.gpu
+
+REL = 2e-4
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _fit_close(fg, fo, dobs_norm2):
+    if fo >= 1e-2 * 0.5 * dobs_norm2:
+        return abs(fg - fo) <= REL * fo
+    return abs(np.sqrt(2 * fg) - np.sqrt(2 * fo)) <= REL * np.sqrt(dobs_norm2)
+
+
+@pytest.fixture(scope="module")
+def gfd():
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    from paper_1905_12795_amd import fd
+    return fd
+
+
+@pytest.mark.timeout(600)
+def test_realistic_full_size_sampled(gfd):
+    g = config("realistic")
+    op = ofd.Problem(g)
+    gp = gfd.Problem(g, dt=op.dt, nt=op.nt)
+    vp = true_model(g)
+    t0 = time.time()
+    dobs = ofd.forward_shots(op, vp).astype(np.float32)          # oracle, all 16 shots
+    _say("oracle d_obs", dobs.shape, "%.1fs" % (time.time() - t0))
+    # traces of two shots through the GPU path at full size
+    tg = gfd.forward_shots(gp, torch.tensor(vp, dtype=torch.float32, device="cuda")).cpu().numpy()
+    for s in (0, 15):
+        e = float(np.linalg.norm(tg[s] - dobs[s]) / np.linalg.norm(dobs[s]))
+        _say("shot", s, "trace rel L2", e)
+        assert e <= REL
+    # the benchmark's batch: 32 particles x 16 shots, autotuned, graph replay
+    X = uniform_particles(g["particles"], g["node_lo"], g["node_hi"], g["particle_seed"])
+    fb = gfd.FitnessBatch([gp], [torch.tensor(dobs, device="cuda")], [0] * len(X))
+    fb.autotune(X)
+    fg = fb(X).cpu().numpy().astype(np.float64)
+    assert np.all(np.isfinite(fg))
+    sample = [0, 17]
+    t0 = time.time()
+    fo, _ = ofd.fitness_batch(op, X[sample].astype(np.float32).astype(np.float64), dobs)
+    _say("oracle fitness of 2 particles %.1fs" % (time.time() - t0), fo, fg[sample])
+    n2 = float(np.sum(dobs.astype(np.float64) ** 2))
+    for i, k in enumerate(sample):
+        assert _fit_close(fg[k], fo[i], n2), (k, fg[k], fo[i])
+
+
+@pytest.mark.timeout(600)
+def test_batched_three_sizes_full_size(gfd):
+    geoms = config("batched")
+    ops = [ofd.Problem(g) for g in geoms]
+    dt = min(o.dt for o in ops)                       # all sizes share dt and nt
+    nt = ofd.n_steps(geoms[0]["tmax"], dt)
+    ops = [ofd.Problem(g, dt=dt, nt=nt) for g in geoms]
+    gps = [gfd.Problem(g, dt=dt, nt=nt) for g in geoms]
+    npart = geoms[0]["particles"]
+    pop = [p % 3 for p in range(npart)]
+    X = uniform_particles(npart, geoms[0]["node_lo"], geoms[0]["node_hi"], geoms[0]["particle_seed"])
+    # observed data: oracle for the sampled size, GPU-free random data for the others
+    rng = np.random.default_rng(11)
+    dobs = []
+    for q, (o, g) in enumerate(zip(ops, geoms)):
+        if q == 0:
+            t0 = time.time()
+            d = ofd.forward_shots(o, true_model(g)).astype(np.float32)
+            _say("oracle d_obs size 0 %.1fs" % (time.time() - t0))
+        else:
+            d = (rng.standard_normal((o.nshots, o.nt, o.nrec)) * 1e-3).astype(np.float32)
+        dobs.append(torch.tensor(d, device="cuda"))
+    fb = gfd.FitnessBatch(gps, dobs, pop)
+    best, us = fb.autotune(X)
+    _say("autotuned", best, us)
+    mixed = fb(X).cpu()
+    # a mixed batch equals per-size batches bit for bit
+    for q in range(3):
+        idx = [p for p in range(npart) if pop[p] == q]
+        sep = gfd.FitnessBatch([gps[q]], [dobs[q]], [0] * len(idx))
+        sep.tuning = fb.tuning
+        assert torch.equal(sep(X[idx]).cpu(), mixed[idx]), q
+    # sampled oracle check on the smallest size (particle 0)
+    t0 = time.time()
+    fo, _ = ofd.fitness_batch(ops[0], X[[0]].astype(np.float32).astype(np.float64),
+                              dobs[0].cpu().numpy())
+    _say("oracle fitness particle 0 %.1fs" % (time.time() - t0), fo, float(mixed[0]))
+    n2 = float(np.sum(dobs[0].cpu().numpy().astype(np.float64) ** 2))
+    assert _fit_close(float(mixed[0]), fo[0], n2)
