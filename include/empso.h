@@ -208,6 +208,50 @@ int empso_time_tuning(const empso_problem *const *probs, int32_t nprob, const fl
                       void *ws, size_t ws_bytes, const empso_tuning *tuning, int32_t reps, float *us_per_step,
                       empso_stream stream);
 
+/* ------------------------------------------------------------------------
+ * Surrogate network (not part of the paper): maps control-node velocities to
+ * a standardised log-misfit so that candidates can be ranked before the
+ * finite-difference fitness. x_hat = (x - lo)/(hi - lo); three hidden layers
+ * h = GELU(W h + b) of width H (exact erf GELU); y = w4 . h3 + b4.
+ * BF16 operands on MFMA with FP32 accumulation; FP32 master parameters and
+ * Adam moments. All buffers are caller-owned device memory.
+ *
+ * FP32 parameter layout (empso_mlp_param_count floats):
+ *   W1 [H][D] | b1 [H] | W2 [H][H] | b2 [H] | W3 [H][H] | b3 [H] | w4 [H] | b4 [1]
+ * BF16 weight copy (empso_mlp_bf16_count values, uint16 bit patterns):
+ *   W1 [H][D] | W2 [H][H] | W3 [H][H]
+ * Training target of a row with fitness f: (log(max(f, 1e-30)) - mu)/sigma;
+ * loss = mean over the rows of (y - target)^2.
+ * ---------------------------------------------------------------------- */
+size_t empso_mlp_param_count(int32_t D, int32_t H);
+size_t empso_mlp_bf16_count(int32_t D, int32_t H);
+/* Workspace bytes for a pass over n rows. */
+size_t empso_mlp_workspace_bytes(int32_t D, int32_t H, int32_t n);
+
+/* Refresh the BF16 weight copy from the FP32 parameters. */
+int empso_mlp_sync_bf16(int32_t D, int32_t H, const float *params_d, uint16_t *wbf16_d, empso_stream stream);
+
+/* y_d[n] = network(X_d[n][D]); lo_d, hi_d: [D] input box. */
+int empso_mlp_predict(int32_t D, int32_t H, const float *params_d, const uint16_t *wbf16_d, const float *lo_d,
+                      const float *hi_d, const float *X_d, int32_t n, float *y_d, void *ws, size_t ws_bytes,
+                      empso_stream stream);
+
+/* Loss and its gradient (FP32, parameter layout) over n rows; row m is
+ * X_d[idx_d[m]] with fitness fit_d[idx_d[m]] (idx_d may be NULL: row m).
+ * grads_d [param_count] and loss_d [1] may be NULL. */
+int empso_mlp_grad(int32_t D, int32_t H, const float *params_d, const uint16_t *wbf16_d, const float *lo_d,
+                   const float *hi_d, const float *X_d, const float *fit_d, const int32_t *idx_d, int32_t n,
+                   float mu, float sigma, float *grads_d, float *loss_d, void *ws, size_t ws_bytes,
+                   empso_stream stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected with the
+ * 1-based step count) on the gradient of empso_mlp_grad, then refresh the
+ * BF16 copy. loss_d [1] receives the loss before the step (may be NULL). */
+int empso_mlp_train_step(int32_t D, int32_t H, float *params_d, uint16_t *wbf16_d, float *adam_m_d, float *adam_v_d,
+                         int32_t step, float lr, const float *lo_d, const float *hi_d, const float *X_d,
+                         const float *fit_d, const int32_t *idx_d, int32_t n, float mu, float sigma, float *loss_d,
+                         void *ws, size_t ws_bytes, empso_stream stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -68,6 +68,18 @@ SIGNATURES = {
                                            ctypes.c_int32, _P(ctypes.c_double), ctypes.c_int32, _vp,
                                            _vp, ctypes.c_size_t, _P(Tuning), _vp]),
     "empso_default_tuning": (ctypes.c_int, [_P(Tuning)]),
+    "empso_mlp_param_count": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32]),
+    "empso_mlp_bf16_count": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32]),
+    "empso_mlp_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "empso_mlp_sync_bf16": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp]),
+    "empso_mlp_predict": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp,
+                                         ctypes.c_int32, _vp, _vp, ctypes.c_size_t, _vp]),
+    "empso_mlp_grad": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                      ctypes.c_int32, ctypes.c_float, ctypes.c_float, _vp, _vp, _vp,
+                                      ctypes.c_size_t, _vp]),
+    "empso_mlp_train_step": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp, _vp, ctypes.c_int32,
+                                            ctypes.c_float, _vp, _vp, _vp, _vp, _vp, ctypes.c_int32,
+                                            ctypes.c_float, ctypes.c_float, _vp, _vp, ctypes.c_size_t, _vp]),
     "empso_autotune_fitness": (ctypes.c_int, [_P(_vp), ctypes.c_int32, _P(_vp), _P(ctypes.c_int32),
                                               ctypes.c_int32, _P(ctypes.c_double), ctypes.c_int32, _vp,
                                               ctypes.c_size_t, _P(Tuning), _P(ctypes.c_float), _vp]),

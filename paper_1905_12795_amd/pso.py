@@ -26,6 +26,7 @@ Initialisation draws x [N][D] uniform in the box, then v [N][D] uniform in
 [-lambda VR, lambda VR]. Fitness values are only compared, never combined,
 so any strictly increasing transform of the fitness gives the same swarm.
 """
+import json
 import math
 
 import numpy as np
@@ -122,3 +123,19 @@ class EMPSO:
         self.gi, self.k, self.evaluations = int(s["gi"]), int(s["k"]), int(s["evaluations"])
         self.rng.bit_generator.state = s["rng"]
         self.history = list(s["history"])
+
+
+def save_checkpoint(path, swarm):
+    """Swarm state (positions, velocities, bests, RNG state, log) in one .npz."""
+    s = swarm.state_dict()
+    meta = json.dumps({"gi": s["gi"], "k": s["k"], "evaluations": s["evaluations"], "rng": s["rng"],
+                       "history": s["history"]})
+    np.savez(path, x=s["x"], v=s["v"], p=s["p"], fp=s["fp"], meta=np.frombuffer(meta.encode(), dtype=np.uint8))
+
+
+def load_checkpoint(path, swarm):
+    """Restore a swarm saved by save_checkpoint (no pickles are loaded)."""
+    d = np.load(path, allow_pickle=False)
+    meta = json.loads(bytes(d["meta"]).decode())
+    swarm.load_state_dict({"x": d["x"], "v": d["v"], "p": d["p"], "fp": d["fp"], **meta})
+    return swarm

@@ -1,0 +1,96 @@
+"""The velocity-model search: EMPSO (or surrogate-screened EMPSO) driving the
+GPU fitness evaluation, with a per-iteration log and checkpoints.
+
+Paper: Algorithm overview section (a generation loop, fitness of every
+particle per generation, statistics and the final population saved at the
+end). Each iteration evaluates the N current positions with the
+finite-difference fitness (`fd.FitnessBatch`), then moves the swarm on the
+host in FP64. In screened mode the surrogate learns from every evaluation
+and picks each particle's move among K candidates.
+"""
+import json
+import math
+import time
+
+import numpy as np
+import torch
+
+from . import fd
+from .pso import EMPSO, load_checkpoint, save_checkpoint  # noqa: F401  (re-exported)
+from .surrogate import RandomRanker, ScreenedEMPSO, Surrogate
+
+
+def observed_data(prob, vp_true, device="cuda"):
+    """Observed traces of the true model, modelled on the GPU (input data)."""
+    return fd.forward_shots(prob, torch.as_tensor(np.asarray(vp_true, np.float32), device=device))
+
+
+def spearman(a, b):
+    ra = np.argsort(np.argsort(a))
+    rb = np.argsort(np.argsort(b))
+    return float(np.corrcoef(ra, rb)[0, 1])
+
+
+def run(geom, dobs, prob, iterations, mode="plain", seed=0, K=16, warmup=2, sur_kw=None, log_path=None,
+        autotune=True, elitist=True, target=None):
+    """Run the search; returns the list of per-iteration records.
+
+    Record fields: iteration, best, mean, median, evaluations (FD, cumulative),
+    wall_s (cumulative, FD + host + surrogate), and in screened mode
+    surrogate_rho (Spearman correlation between the surrogate's prediction and
+    the FD misfit of the evaluated particles, measured before it trains on
+    them) and surrogate_mae (mean absolute error of the standardised
+    log-misfit). If `target` is given the run stops once best <= target.
+    """
+    N = geom["particles"]
+    lo, hi = geom["node_lo"], geom["node_hi"]
+    fb = fd.FitnessBatch([prob], [dobs], [0] * N)
+    kw = dict(gen=iterations, seed=seed, elitist=elitist)
+    if mode == "plain":
+        swarm = EMPSO(lo, hi, N, **kw)
+        sur = None
+    elif mode == "screened":
+        sur = Surrogate(lo, hi, seed=seed, **(sur_kw or {}))
+        swarm = ScreenedEMPSO(lo, hi, N, sur, K=K, warmup=warmup, **kw)
+    elif mode == "random":
+        sur = None
+        swarm = ScreenedEMPSO(lo, hi, N, RandomRanker(seed), K=K, warmup=warmup, **kw)
+    else:
+        raise ValueError(mode)
+    if autotune:
+        fb.autotune(swarm.ask())
+    out = []
+    logf = open(log_path, "a") if log_path else None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for it in range(iterations):
+        x = swarm.ask()
+        f = fb(x).cpu().numpy().astype(np.float64)
+        rec_extra = {}
+        if isinstance(sur, Surrogate) and sur.count >= N * warmup:
+            pred = sur.predict(x)
+            ok = np.isfinite(f)
+            lf = (np.log(np.maximum(f[ok], 1e-30)) - sur.mu) / sur.sigma
+            rec_extra = {"surrogate_rho": spearman(pred[ok], f[ok]),
+                         "surrogate_mae": float(np.mean(np.abs(pred[ok] - lf)))}
+        rec = dict(swarm.tell(f))
+        rec.update(rec_extra)
+        rec["wall_s"] = time.perf_counter() - t0
+        rec["mode"] = mode
+        out.append(rec)
+        if logf:
+            logf.write(json.dumps(rec) + "\n")
+            logf.flush()
+        if target is not None and rec["best"] <= target:
+            break
+    if logf:
+        logf.close()
+    return out
+
+
+def evals_to_reach(history, target):
+    """(FD evaluations, wall seconds) when the best misfit first reaches target, else (inf, inf)."""
+    for r in history:
+        if r["best"] <= target:
+            return r["evaluations"], r["wall_s"]
+    return math.inf, math.inf

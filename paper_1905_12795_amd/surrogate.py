@@ -1,0 +1,230 @@
+"""Learned surrogate of the fitness and the screening policy built on it.
+
+Not part of the paper. A multilayer perceptron (HIP library, BF16 MFMA with
+FP32 accumulation, FP32 Adam) learns the standardised log-misfit of
+control-node vectors from the (particle, misfit) pairs that the
+finite-difference fitness produces during the search. Before each
+finite-difference evaluation, every particle proposes several candidate
+moves (independent draws of Eq. 1's random vectors); the network ranks them
+and only each particle's best-ranked candidate is evaluated, so the number of
+finite-difference evaluations per iteration is unchanged while the moves that
+reach the solver are better on average.
+"""
+import ctypes
+
+import numpy as np
+import torch
+
+from ._lib import check, lib
+from .pso import EMPSO
+from workloads.models import mlp_init
+
+
+def _ptr(t):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def flatten_params(layers):
+    """[(W1,b1),(W2,b2),(W3,b3),(w4,b4)] -> flat FP32 vector in the library's layout."""
+    parts = []
+    for W, b in layers[:-1]:
+        parts += [np.asarray(W, np.float32).ravel(), np.asarray(b, np.float32).ravel()]
+    W4, b4 = layers[-1]
+    parts += [np.asarray(W4, np.float32).ravel(), np.asarray(b4, np.float32).ravel()]
+    return np.concatenate(parts)
+
+
+def unflatten_params(flat, D, H):
+    flat = np.asarray(flat, dtype=np.float64)
+    out, k = [], 0
+    for fin in (D, H, H):
+        W = flat[k:k + H * fin].reshape(H, fin); k += H * fin
+        b = flat[k:k + H]; k += H
+        out.append((W, b))
+    w4 = flat[k:k + H].reshape(1, H); k += H
+    b4 = flat[k:k + 1]; k += 1
+    out.append((w4, b4))
+    return out
+
+
+class MLP:
+    """Device-resident network: FP32 parameters, BF16 weight copy, Adam moments."""
+
+    def __init__(self, lo, hi, H=256, seed=0, device="cuda"):
+        self.lo = torch.tensor(np.asarray(lo, np.float32), device=device)
+        self.hi = torch.tensor(np.asarray(hi, np.float32), device=device)
+        self.D, self.H = int(self.lo.numel()), int(H)
+        self.P = lib.empso_mlp_param_count(self.D, self.H)
+        self.PB = lib.empso_mlp_bf16_count(self.D, self.H)
+        init = flatten_params(mlp_init([self.D, self.H, self.H, self.H, 1], seed))
+        assert init.size == self.P
+        self.params = torch.tensor(init, device=device)
+        self.wbf16 = torch.empty(self.PB, dtype=torch.int16, device=device)
+        self.m = torch.zeros(self.P, dtype=torch.float32, device=device)
+        self.v = torch.zeros(self.P, dtype=torch.float32, device=device)
+        self.step = 0
+        self._ws = {}
+        check(lib.empso_mlp_sync_bf16(self.D, self.H, _ptr(self.params), _ptr(self.wbf16), _stream()))
+
+    def _workspace(self, n):
+        if n not in self._ws:
+            nb = lib.empso_mlp_workspace_bytes(self.D, self.H, n)
+            if nb == 0:
+                raise ValueError("bad MLP shape")
+            self._ws[n] = torch.empty(nb, dtype=torch.uint8, device=self.params.device)
+        return self._ws[n]
+
+    def predict(self, X):
+        """X: device FP32 [n][D] -> device FP32 [n] (standardised log-misfit)."""
+        n = int(X.shape[0])
+        y = torch.empty(n, dtype=torch.float32, device=X.device)
+        ws = self._workspace(n)
+        check(lib.empso_mlp_predict(self.D, self.H, _ptr(self.params), _ptr(self.wbf16), _ptr(self.lo),
+                                    _ptr(self.hi), _ptr(X), n, _ptr(y), _ptr(ws), ws.numel(), _stream()))
+        return y
+
+    def grad(self, X, fit, idx, mu, sigma):
+        n = int(idx.numel()) if idx is not None else int(X.shape[0])
+        g = torch.empty(self.P, dtype=torch.float32, device=X.device)
+        loss = torch.empty(1, dtype=torch.float32, device=X.device)
+        ws = self._workspace(n)
+        check(lib.empso_mlp_grad(self.D, self.H, _ptr(self.params), _ptr(self.wbf16), _ptr(self.lo), _ptr(self.hi),
+                                 _ptr(X), _ptr(fit), _ptr(idx), n, float(mu), float(sigma), _ptr(g), _ptr(loss),
+                                 _ptr(ws), ws.numel(), _stream()))
+        return loss, g
+
+    def train_step(self, X, fit, idx, mu, sigma, lr):
+        n = int(idx.numel()) if idx is not None else int(X.shape[0])
+        loss = torch.empty(1, dtype=torch.float32, device=X.device)
+        ws = self._workspace(n)
+        self.step += 1
+        check(lib.empso_mlp_train_step(self.D, self.H, _ptr(self.params), _ptr(self.wbf16), _ptr(self.m),
+                                       _ptr(self.v), self.step, float(lr), _ptr(self.lo), _ptr(self.hi), _ptr(X),
+                                       _ptr(fit), _ptr(idx), n, float(mu), float(sigma), _ptr(loss), _ptr(ws),
+                                       ws.numel(), _stream()))
+        return loss
+
+
+class Surrogate:
+    """MLP plus the on-device dataset of (nodes, FD fitness) pairs it learns from."""
+
+    def __init__(self, lo, hi, H=256, seed=0, lr=1e-3, batch=256, steps_per_update=64, capacity=65536,
+                 device="cuda"):
+        self.net = MLP(lo, hi, H=H, seed=seed, device=device)
+        self.D = self.net.D
+        self.lr, self.batch, self.steps_per_update = float(lr), int(batch), int(steps_per_update)
+        self.X = torch.empty((capacity, self.D), dtype=torch.float32, device=device)
+        self.f = torch.empty(capacity, dtype=torch.float32, device=device)
+        self.logf = []                       # host copy of log-fitness for the target scaling
+        self.count = 0
+        self.rng = np.random.Generator(np.random.PCG64(seed + 1))
+        self.mu, self.sigma = 0.0, 1.0
+
+    def add(self, X, fit):
+        """Append evaluated particles: X host [k][D], fit host or device [k]."""
+        k = len(X)
+        if self.count + k > self.X.shape[0]:
+            raise ValueError("surrogate dataset full")
+        self.X[self.count:self.count + k] = torch.as_tensor(np.asarray(X, np.float32), device=self.X.device)
+        fit_t = torch.as_tensor(fit, dtype=torch.float32).to(self.X.device)
+        self.f[self.count:self.count + k] = fit_t
+        fh = np.asarray(fit_t.cpu(), dtype=np.float64)
+        self.logf.extend(np.log(np.maximum(fh[np.isfinite(fh)], 1e-30)).tolist())
+        self.count += k
+        lf = np.asarray(self.logf)
+        self.mu = float(lf.mean())
+        self.sigma = float(max(lf.std(), 1e-6))
+
+    def train(self, steps=None):
+        """Adam steps on random mini-batches of the dataset; returns the last loss."""
+        steps = self.steps_per_update if steps is None else steps
+        loss = None
+        for _ in range(steps):
+            b = min(self.batch, self.count)
+            idx = torch.as_tensor(self.rng.integers(0, self.count, b).astype(np.int32), device=self.X.device)
+            loss = self.net.train_step(self.X, self.f, idx, self.mu, self.sigma, self.lr)
+        return None if loss is None else float(loss.item())
+
+    def predict(self, X):
+        """Host [n][D] -> host predicted standardised log-misfit [n]."""
+        Xd = torch.as_tensor(np.asarray(X, np.float32), device=self.X.device)
+        return self.net.predict(Xd).cpu().numpy().astype(np.float64)
+
+
+class RandomRanker:
+    """Ablation of the surrogate: ranks candidates at random (seeded), so the
+    screened search degenerates to EMPSO with an extra choice among K draws."""
+
+    def __init__(self, seed=0):
+        self.rng = np.random.Generator(np.random.PCG64(seed + 7))
+        self.count = 0
+        self.mu, self.sigma = 0.0, 1.0
+
+    def add(self, X, fit):
+        self.count += len(X)
+
+    def train(self, steps=None):
+        return None
+
+    def predict(self, X):
+        return self.rng.random(len(X))
+
+
+class ScreenedEMPSO(EMPSO):
+    """EMPSO whose Eq. 1-2 move is chosen among K candidate draws per particle
+    by the surrogate. With K = 1 (or before `warmup` iterations) it is EMPSO.
+
+    The draw order per iteration: K pairs (u1, u2) of [N][D] uniforms, then the
+    elitist-mutation draws as in EMPSO.
+    """
+
+    def __init__(self, lo, hi, n, surrogate, K=16, warmup=2, **kw):
+        super().__init__(lo, hi, n, **kw)
+        self.sur = surrogate
+        self.K = int(K)
+        self.warmup = int(warmup)
+        self.last_rank_corr = None
+
+    def tell(self, f):
+        f = np.asarray(f, dtype=np.float64).copy()
+        f[~np.isfinite(f)] = np.inf
+        self.sur.add(self.x, np.where(np.isfinite(f), f, np.float32(3e38)))
+        self.sur.train()
+        if self.k + 1 < self.warmup or self.K <= 1:
+            return super().tell(f)
+        # bests (as in EMPSO.tell)
+        self.evaluations += self.N
+        better = f < self.fp
+        self.fp = np.where(better, f, self.fp)
+        self.p = np.where(better[:, None], self.x, self.p)
+        self.gi = int(np.argmin(self.fp))
+        self.k += 1
+        g = self.p[self.gi]
+        cand_x, cand_v = [], []
+        for _ in range(self.K):
+            u1 = self.rng.random((self.N, self.D))
+            u2 = self.rng.random((self.N, self.D))
+            v = self.chi * (self.v + self.c1 * u1 * (self.p - self.x) + self.c2 * u2 * (g - self.x))
+            v = np.minimum(np.maximum(v, -self.vclamp), self.vclamp)
+            cand_v.append(v)
+            cand_x.append(np.minimum(np.maximum(self.x + v, self.lo), self.hi))
+        cx = np.stack(cand_x)                       # [K][N][D]
+        pred = self.sur.predict(cx.reshape(-1, self.D)).reshape(self.K, self.N)
+        pick = np.argmin(pred, axis=0)
+        x = cx[pick, np.arange(self.N)]
+        v = np.stack(cand_v)[pick, np.arange(self.N)]
+        if self.elitist and self.k >= self.em_start and self.nm > 0:
+            ru = self.rng.random((self.nm, self.D))
+            rn = self.rng.standard_normal((self.nm, self.D))
+            worst = np.argsort(-f, kind="stable")[:self.nm]
+            mut = np.where(ru < self.p_em, g + 0.1 * self.vr * rn, g)
+            x[worst] = np.minimum(np.maximum(mut, self.lo), self.hi)
+        self.x, self.v = x, v
+        self.history.append({"iteration": self.k, "best": float(self.fg),
+                             "mean": float(np.mean(f[np.isfinite(f)])) if np.any(np.isfinite(f)) else float("inf"),
+                             "median": float(np.median(f)), "evaluations": self.evaluations})
+        return self.history[-1]

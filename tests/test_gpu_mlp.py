@@ -1,0 +1,118 @@
+"""GPU parity of the surrogate network (BF16 MFMA, FP32 accumulation) against the FP64 oracle MLP.
+
+Bar, from the BF16 operands (8-bit significand, relative rounding 2^-9 per
+operand, three layers): network output within 2e-2 relative L2 of the FP64
+network with the same FP32 parameters; loss within 2e-2; every gradient
+tensor with cosine similarity >= 0.99 to the FP64 gradient.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import mlp as omlp
+from workloads.configs import config
+from workloads.models import mlp_init, uniform_particles
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sur():
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    from paper_1905_12795_amd import surrogate
+    return surrogate
+
+
+def _case(D, H, n, seed):
+    rng = np.random.default_rng(seed)
+    lo = rng.uniform(1400, 2500, D)
+    hi = lo + rng.uniform(500, 2500, D)
+    X = uniform_particles(n, lo, hi, seed + 1).astype(np.float32).astype(np.float64)
+    fit = np.exp(rng.normal(3.0, 1.0, n)).astype(np.float32)
+    return lo, hi, X, fit
+
+
+def _oracle_layers(net, sur):
+    return sur.unflatten_params(net.params.cpu().numpy(), net.D, net.H)
+
+
+@pytest.mark.parametrize("D,H,n", [(60, 256, 1024), (13, 40, 77)])
+def test_forward_matches_oracle(sur, D, H, n):
+    lo, hi, X, _ = _case(D, H, n, 1)
+    net = sur.MLP(lo, hi, H=H, seed=3)
+    y = net.predict(torch.tensor(X, dtype=torch.float32, device="cuda")).cpu().numpy()
+    yo, _ = omlp.forward(_oracle_layers(net, sur), X, lo.astype(np.float32).astype(np.float64),
+                         hi.astype(np.float32).astype(np.float64))
+    rel = np.linalg.norm(y - yo) / np.linalg.norm(yo)
+    assert rel <= 2e-2, rel
+
+
+@pytest.mark.parametrize("D,H,n", [(60, 256, 512), (13, 40, 77)])
+def test_gradient_matches_oracle(sur, D, H, n):
+    lo, hi, X, fit = _case(D, H, n, 2)
+    net = sur.MLP(lo, hi, H=H, seed=4)
+    lf = np.log(fit.astype(np.float64))
+    mu, sigma = float(lf.mean()), float(lf.std())
+    Xd = torch.tensor(X, dtype=torch.float32, device="cuda")
+    fd_ = torch.tensor(fit, device="cuda")
+    loss, g = net.grad(Xd, fd_, None, mu, sigma)
+    t = (np.log(fit.astype(np.float64)) - np.float32(mu)) / np.float32(sigma)
+    lo_, hi_ = lo.astype(np.float32).astype(np.float64), hi.astype(np.float32).astype(np.float64)
+    lo_ref, gr = omlp.loss_and_grads(_oracle_layers(net, sur), X, t, lo_, hi_)
+    assert abs(float(loss.item()) - lo_ref) <= 2e-2 * lo_ref
+    gg = sur.unflatten_params(g.cpu().numpy(), D, H)
+    for (gW, gb), (oW, ob) in zip(gg, gr):
+        for a, b in ((gW, oW), (gb, ob)):
+            a, b = np.ravel(a), np.ravel(b)
+            cos = float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b)))
+            assert cos >= 0.99, cos
+
+
+def test_index_gather_equals_dense_rows(sur):
+    lo, hi, X, fit = _case(17, 64, 300, 5)
+    net = sur.MLP(lo, hi, H=64, seed=5)
+    idx = np.random.default_rng(6).integers(0, 300, 96).astype(np.int32)
+    Xd = torch.tensor(X, dtype=torch.float32, device="cuda")
+    fd_ = torch.tensor(fit, device="cuda")
+    l1, g1 = net.grad(Xd, fd_, torch.tensor(idx, device="cuda"), 1.0, 2.0)
+    l2, g2 = net.grad(Xd[idx].contiguous(), fd_[idx].contiguous(), None, 1.0, 2.0)
+    assert torch.equal(l1, l2) and torch.equal(g1, g2)
+
+
+def test_first_adam_step_moves_by_lr_sign(sur):
+    lo, hi, X, fit = _case(20, 64, 128, 7)
+    net = sur.MLP(lo, hi, H=64, seed=8)
+    Xd = torch.tensor(X, dtype=torch.float32, device="cuda")
+    fd_ = torch.tensor(fit, device="cuda")
+    _, g = net.grad(Xd, fd_, None, 3.0, 1.0)
+    p0 = net.params.clone()
+    lr = 1e-3
+    net.train_step(Xd, fd_, None, 3.0, 1.0, lr)
+    dp = (net.params - p0).cpu().numpy()
+    gh = g.cpu().numpy()
+    big = np.abs(gh) > 1e-4
+    assert big.sum() > 100
+    assert np.allclose(dp[big], -lr * np.sign(gh[big]), rtol=1e-3, atol=1e-7)
+
+
+def test_training_reduces_loss_on_smooth_target(sur):
+    g = config("realistic")
+    lo, hi = g["node_lo"], g["node_hi"]
+    X = uniform_particles(2048, lo, hi, 9)
+    xn = (X - lo) / (hi - lo)
+    fit = np.exp(2.0 + 3.0 * np.sum((xn - 0.4) ** 2, axis=1) / X.shape[1] * 4).astype(np.float32)
+    s = sur.Surrogate(lo, hi, H=256, seed=10, lr=1e-3, batch=256)
+    s.add(X, fit)
+    first = s.train(steps=1)
+    curve = [s.train(steps=100) for _ in range(6)]
+    print("loss", first, curve, flush=True)
+    last = curve[-1]
+    assert last < 0.25 * first, (first, curve)
+    # ranking quality on fresh points
+    Xt = uniform_particles(512, lo, hi, 11)
+    xt = (Xt - lo) / (hi - lo)
+    ft = np.sum((xt - 0.4) ** 2, axis=1)
+    pred = s.predict(Xt)
+    rho = np.corrcoef(np.argsort(np.argsort(pred)), np.argsort(np.argsort(ft)))[0, 1]
+    print("spearman", rho, flush=True)
+    assert rho > 0.7, rho

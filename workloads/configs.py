@@ -20,7 +20,7 @@ import numpy as np
 
 from .models import two_layer, layered_faulted
 
-CONFIG_NAMES = ("tiny", "realistic", "batched", "surrogate", "full")
+CONFIG_NAMES = ("tiny", "realistic", "batched", "surrogate", "full", "mini")
 
 
 def _prior_box(nz, dz, ncz, ncx, v0=1500.0, v1=5500.0, lo_min=1400.0, hi_max=6000.0):
@@ -90,6 +90,18 @@ def config(name):
         return out
     if name in ("full", 4):
         return _layered_geometry(601, 1841, 5, 32, 10, 6.0, 4.0, 8, 20, seed=8, pseed=9, npart=128)
+    if name == "mini":
+        # a reduced realistic search used to compare plain and screened swarms
+        # quickly: 1 km x 3 km at 10 m, 4 shots, 151 receivers, 4 Hz, 1.5 s,
+        # 3 x 6 nodes, 32 particles; true model layered and faulted, 1500-2800 m/s
+        g = _layered_geometry(101, 301, 10, 4, 20, 4.0, 1.5, 3, 6, seed=3, pseed=1, npart=32)
+        g["src"] = [[0.0, x] for x in (500.0, 1200.0, 1800.0, 2500.0)]
+        g["model"] = {"kind": "layered_faulted", "seed": 3, "v_bottom": 2800.0}
+        zrow = np.arange(3) * 1000.0 / 2
+        vprior = 1500.0 + 4000.0 * zrow / 3000.0
+        g["node_lo"] = np.repeat(np.maximum(1400.0, 0.7 * vprior), 6)
+        g["node_hi"] = np.repeat(np.minimum(6000.0, 1.3 * vprior), 6)
+        return g
     raise KeyError(name)
 
 
@@ -101,5 +113,6 @@ def true_model(geom):
                           m["v_top"], m["v_bottom"], m["seed"])
         return vp
     if m["kind"] == "layered_faulted":
-        return layered_faulted(geom["nz"], geom["nx"], geom["dz"], geom["dx"], m["seed"])
+        return layered_faulted(geom["nz"], geom["nx"], geom["dz"], geom["dx"], m["seed"],
+                               v_bottom=m.get("v_bottom", 5500.0))
     raise KeyError(m["kind"])

@@ -84,3 +84,15 @@ def uniform_particles(n, lo, hi, seed):
     hi = np.asarray(hi, dtype=np.float64)
     rng = np.random.default_rng(seed)
     return lo + (hi - lo) * rng.random((n, lo.size))
+
+
+def mlp_init(sizes, seed):
+    """Seeded initial weights of a fully connected network: per layer
+    W ~ U(-1/sqrt(fan_in), 1/sqrt(fan_in)) of shape [fan_out][fan_in], then
+    b ~ the same range. Returns [(W, b), ...] in float64."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for fin, fout in zip(sizes[:-1], sizes[1:]):
+        s = 1.0 / np.sqrt(fin)
+        out.append((rng.uniform(-s, s, (fout, fin)), rng.uniform(-s, s, fout)))
+    return out
