@@ -424,12 +424,12 @@ __device__ __forceinline__ void sample_receivers(const RunDesc &R, int n, int J0
 }
 
 // Whole-wavefront lane shifts (DPP wave_shr:1 / wave_shl:1): the value of
-// lane-1 / lane+1. The lane without a source (0 resp. 63) gets 0.
+// lane-1 / lane+1. The lane without a source (0 resp. 63) reads 0 (bound_ctrl).
 __device__ __forceinline__ float from_lane_below(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, true));
 }
 __device__ __forceinline__ float from_lane_above(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, true));
 }
 
 // T time steps n -> n+T for every tile, all levels in registers.
@@ -446,10 +446,11 @@ __device__ __forceinline__ float from_lane_above(float v) {
 // other store gets an out-of-range buffer offset and is dropped by the
 // hardware, so the loop body has no branches. Rows above or below the stored
 // field read as zero for the same reason.
-// Points outside the padded grid are forced to zero at every level.
+// Points outside the padded grid need no masking: C is zero there and so are
+// the incoming u and delta, so they stay exactly zero at every level.
 // Receiver samples of each level (u^{n+t-1} on the receiver row) are kept in
 // registers and accumulated after the march by the owning lanes.
-template <int M, int T>
+template <int M, int T, bool ISO>
 __global__ __launch_bounds__(256) void k_tb(const RunDesc *__restrict__ runs, const int4 *__restrict__ tiles,
                                             int ntiles, int n, int par) {
     constexpr int NS = kQueue;
@@ -465,13 +466,20 @@ __global__ __launch_bounds__(256) void k_tb(const RunDesc *__restrict__ runs, co
     const RunDesc R = runs[t.x];
     const int S = R.S;
     const int bot = R.Nz + kRing;                   // end of the stored rows of the padded grid
-    // (selects, not R.u[par]: a runtime index would move R to scratch memory)
-    const rsrc_t uin = make_rsrc(par ? R.u[1] : R.u[0], R.fbytes);
-    const rsrc_t din = make_rsrc(par ? R.d[1] : R.d[0], R.fbytes);
-    const rsrc_t uout = make_rsrc(par ? R.u[0] : R.u[1], R.fbytes);
-    const rsrc_t dout = make_rsrc(par ? R.d[0] : R.d[1], R.fbytes);
+    // One buffer resource spans the run's four contiguous fields u0 | u1 | d0 | d1;
+    // the byte offsets below select the input and output buffers (selects,
+    // not R.u[par]: a runtime index would move R to scratch memory). Reads
+    // that run past a field land in the next field's zero ring or beyond the
+    // range (zero); both only feed rows that are never stored.
+    const rsrc_t F = make_rsrc(R.u[0], 4u * R.fbytes);
+    const int fb = (int)R.fbytes;
+    const int uin = par ? fb : 0, din = par ? 3 * fb : 2 * fb;
+    const int uout = par ? 0 : fb, dout = par ? 2 * fb : 3 * fb;
     const rsrc_t Cf = make_rsrc(R.C, R.fbytes);
     const int c = t.z + 4 * lane;                   // stored column of this lane's first element
+    // Lanes past the stored row work on its last four columns instead: that
+    // tail is zero in u, delta and C, the lanes compute zeros there and any
+    // store they make writes zeros into the tail, which keeps it zero.
     const int cc = min(c, S - 4);                   // past the row: its zero tail
     const int J0 = c - kRing;
     const bool own = (lane >= T) && (lane < 64 - T);
@@ -480,15 +488,14 @@ __global__ __launch_bounds__(256) void k_tb(const RunDesc *__restrict__ runs, co
     const int lcol = 4 * cc;                        // byte offset of the lane's columns in a row
     const int rowb = 4 * S;                         // bytes per stored row
 
-    float axk[4];
-    bool inx[4];
+    float axk[4], srcm[4];
     bool xdamp = false;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int J = J0 + k;
-        inx[k] = (J >= 0) && (J < R.Nx);
-        axk[k] = inx[k] ? gld(R.ax + J) : 0.0f;
+        axk[k] = (J >= 0 && J < R.Nx) ? gld(R.ax + J) : 0.0f;
         xdamp |= axk[k] != 0.0f;
+        srcm[k] = (c + k == R.srcC) ? 1.0f : 0.0f;     // this lane holds the source column
     }
     const bool tile_xdamp = __any(xdamp);
     float fsrc[T];
@@ -498,8 +505,8 @@ __global__ __launch_bounds__(256) void k_tb(const RunDesc *__restrict__ runs, co
     const int rs = s0 - 4 * (T - 1);                // level-1 row of the first march step
     float4 q0[NS], qu[TQ][NS], qd[TQ][ND], dq[2], cq[T][2], rec[T];
 #pragma unroll
-    for (int j = 0; j < 9; ++j) q0[j] = bld4(uin, (rs - 4 + j) * rowb + lcol);
-    dq[0] = bld4(din, rs * rowb + lcol);
+    for (int j = 0; j < 9; ++j) q0[j] = bld4(F, uin + (rs - 4 + j) * rowb + lcol);
+    dq[0] = bld4(F, din + rs * rowb + lcol);
 #pragma unroll
     for (int l = 0; l < T; ++l) {
         cq[l][0] = bld4(Cf, (rs - 4 * l) * rowb + lcol);
@@ -516,8 +523,8 @@ __global__ __launch_bounds__(256) void k_tb(const RunDesc *__restrict__ runs, co
 
     // One march step: k = (step index) mod 10, known at compile time.
     auto step = [&](const int k, const int r1) {
-        q0[(k + 9) % NS] = bld4(uin, (r1 + 5) * rowb + lcol);
-        dq[(k + 1) & 1] = bld4(din, (r1 + 1) * rowb + lcol);
+        q0[(k + 9) % NS] = bld4(F, uin + (r1 + 5) * rowb + lcol);
+        dq[(k + 1) & 1] = bld4(F, din + (r1 + 1) * rowb + lcol);
 #pragma unroll
         for (int l = 0; l < T; ++l) cq[l][(k + 1) & 1] = bld4(Cf, (r1 + 1 - 4 * l) * rowb + lcol);
         float4 un = make_float4(0.f, 0.f, 0.f, 0.f), dn = un;
@@ -532,7 +539,6 @@ __global__ __launch_bounds__(256) void k_tb(const RunDesc *__restrict__ runs, co
             const float4 d4 = (l == 0) ? dq[k & 1] : qd[l > 0 ? l - 1 : 0][(k + 1) % ND];
             const float4 C4 = cq[l][k & 1];
             const int r = r1 - 4 * l;
-            const bool rowin = (r >= kRing) && (r < bot);
             const float v[12] = {from_lane_below(ce.x), from_lane_below(ce.y),
                                  from_lane_below(ce.z), from_lane_below(ce.w),
                                  ce.x, ce.y, ce.z, ce.w,
@@ -546,24 +552,33 @@ __global__ __launch_bounds__(256) void k_tb(const RunDesc *__restrict__ runs, co
             const float Cv[4] = {C4.x, C4.y, C4.z, C4.w};
             const float azr = sld(R.az + min(max(r - kRing, 0), R.Nz - 1));
             const bool damped = tile_xdamp || (azr != 0.0f);
-            const bool srow = (r == R.srcS);
+            const float fs = (r == R.srcS) ? fsrc[l] : 0.0f;   // wave-uniform
             float uo[4], dd[4];
 #pragma unroll
             for (int k2 = 0; k2 < 4; ++k2) {
                 const float u = v[4 + k2];
-                // Laplacian as a sum of small terms c_k ((u_{+k} + u_{-k}) - 2u),
-                // farthest neighbours first: the centre weight is never formed,
-                // so no large partial sum cancels (FP32 accuracy over long runs).
-                const float u2 = u + u;
-                float lap = R.cz4 * ((pz4[k2] + mz4[k2]) - u2);
-                lap = fmaf(R.cz3, (pz3[k2] + mz3[k2]) - u2, lap);
-                lap = fmaf(R.cz2, (pz2[k2] + mz2[k2]) - u2, lap);
-                lap = fmaf(R.cz1, (pz1[k2] + mz1[k2]) - u2, lap);
-                lap = fmaf(R.cx4, (v[0 + k2] + v[8 + k2]) - u2, lap);
-                lap = fmaf(R.cx3, (v[1 + k2] + v[7 + k2]) - u2, lap);
-                lap = fmaf(R.cx2, (v[2 + k2] + v[6 + k2]) - u2, lap);
-                lap = fmaf(R.cx1, (v[3 + k2] + v[5 + k2]) - u2, lap);
-                lap += (srow && (c + k2 == R.srcC)) ? fsrc[l] : 0.0f;
+                // Laplacian as a sum of small terms, farthest neighbours first:
+                // c_k ((u_{+k} + u_{-k}) - 2u) per axis, or with dz = dx
+                // c_k (((z pair) + (x pair)) - 4u). The centre weight is never
+                // formed, so no large partial sum cancels (FP32 accuracy over
+                // long runs).
+                float lap;
+                if (ISO) {
+                    lap = R.cz4 * fmaf(-4.0f, u, (pz4[k2] + mz4[k2]) + (v[0 + k2] + v[8 + k2]));
+                    lap = fmaf(R.cz3, fmaf(-4.0f, u, (pz3[k2] + mz3[k2]) + (v[1 + k2] + v[7 + k2])), lap);
+                    lap = fmaf(R.cz2, fmaf(-4.0f, u, (pz2[k2] + mz2[k2]) + (v[2 + k2] + v[6 + k2])), lap);
+                    lap = fmaf(R.cz1, fmaf(-4.0f, u, (pz1[k2] + mz1[k2]) + (v[3 + k2] + v[5 + k2])), lap);
+                } else {
+                    lap = R.cz4 * fmaf(-2.0f, u, pz4[k2] + mz4[k2]);
+                    lap = fmaf(R.cz3, fmaf(-2.0f, u, pz3[k2] + mz3[k2]), lap);
+                    lap = fmaf(R.cz2, fmaf(-2.0f, u, pz2[k2] + mz2[k2]), lap);
+                    lap = fmaf(R.cz1, fmaf(-2.0f, u, pz1[k2] + mz1[k2]), lap);
+                    lap = fmaf(R.cx4, fmaf(-2.0f, u, v[0 + k2] + v[8 + k2]), lap);
+                    lap = fmaf(R.cx3, fmaf(-2.0f, u, v[1 + k2] + v[7 + k2]), lap);
+                    lap = fmaf(R.cx2, fmaf(-2.0f, u, v[2 + k2] + v[6 + k2]), lap);
+                    lap = fmaf(R.cx1, fmaf(-2.0f, u, v[3 + k2] + v[5 + k2]), lap);
+                }
+                lap = fmaf(srcm[k2], fs, lap);
                 // The damped form reduces bit for bit to the undamped one
                 // when a = 0 ((1-a) dv = dv, rcp(1) = 1), so a point's result
                 // does not depend on which branch its tile takes.
@@ -575,9 +590,8 @@ __global__ __launch_bounds__(256) void k_tb(const RunDesc *__restrict__ runs, co
                 } else {
                     d = fmaf(Cv[k2], lap, dv[k2]);
                 }
-                const bool in = rowin && inx[k2];
-                dd[k2] = in ? d : 0.0f;
-                uo[k2] = in ? u + d : 0.0f;
+                dd[k2] = d;
+                uo[k2] = u + d;
             }
             if (r == R.recS) rec[l] = ce;
             un = make_float4(uo[0], uo[1], uo[2], uo[3]);
@@ -589,9 +603,9 @@ __global__ __launch_bounds__(256) void k_tb(const RunDesc *__restrict__ runs, co
         }
         const int rT = r1 - 4 * (T - 1);
         const bool ok = own && (rT >= s0) && (rT < s1);
-        const int a = ok ? rT * rowb + lcol : kDrop;   // dropped by the range check
-        bst4(uout, a, un);
-        bst4(dout, a, dn);
+        const int o = rT * rowb + lcol;
+        bst4(F, ok ? uout + o : kDrop, un);            // kDrop: dropped by the range check
+        bst4(F, ok ? dout + o : kDrop, dn);
     };
 
     // fill: the first 8(T-1) steps produce no owned output yet
@@ -605,8 +619,12 @@ __global__ __launch_bounds__(256) void k_tb(const RunDesc *__restrict__ runs, co
         for (int kk = 0; kk < NS; ++kk) step((FILL + kk) % NS, rs + j + kk);
     }
     if (R.recS >= s0 && R.recS < s1 && own) {
+        // reload the descriptor (the receiver tables need not stay live in
+        // scalar registers during the march)
+        const RunDesc *Rp = runs + t.x;
+        asm volatile("" : "+s"(Rp));
 #pragma unroll
-        for (int l = 0; l < T; ++l) sample_receivers(R, n + l, J0, rec[l]);
+        for (int l = 0; l < T; ++l) sample_receivers(*Rp, n + l, J0, rec[l]);
     }
 }
 
@@ -718,6 +736,7 @@ struct Layout {
     std::vector<size_t> field_of_run;      // byte offset of u[0] (u[1], d[0], d[1] follow)
     std::vector<size_t> acc_of_run;
     int ntiles, ntiles1;                   // tiles of the main depth and of single steps
+    bool iso;                              // every problem has dz == dx
 };
 
 // Workspace layout for the runs (particle-major, shot-minor); independent of
@@ -729,7 +748,9 @@ static Layout make_layout(const std::vector<const empso_problem *> &pp, const st
     const int nruns = (int)runs.size();
     int cap = 0;
     L.ntiles = L.ntiles1 = 0;
+    L.iso = true;
     for (const RunSpec &r : runs) {
+        L.iso = L.iso && (r.p->g.dz == r.p->g.dx);
         cap += tiles_of(r.p, kMinBz, kMaxT);
         L.ntiles += tiles_of(r.p, bz, T);
         L.ntiles1 += tiles_of(r.p, kTailBz, 1);
@@ -782,14 +803,17 @@ static std::mutex g_plan_mu;
 static std::vector<Plan *> g_plans;   // small LRU
 static const size_t kMaxPlans = 8;
 
-static int launch_tb(int bz, int T, const RunDesc *runs, const int4 *tiles, int ntiles, int n, int par,
+static int launch_tb(int bz, int T, bool iso, const RunDesc *runs, const int4 *tiles, int ntiles, int n, int par,
                      hipStream_t st) {
     int blocks = (ntiles + 3) / 4;
     blocks = (blocks + 7) / 8 * 8;
-#define EMPSO_TB_CASE(B, TT)                                                         \
-    if (bz == B && T == TT) {                                                        \
-        k_tb<B / kQueue, TT><<<blocks, 256, 0, st>>>(runs, tiles, ntiles, n, par);   \
-        return EMPSO_OK;                                                             \
+#define EMPSO_TB_CASE(B, TT)                                                                 \
+    if (bz == B && T == TT) {                                                                \
+        if (iso)                                                                             \
+            k_tb<B / kQueue, TT, true><<<blocks, 256, 0, st>>>(runs, tiles, ntiles, n, par);  \
+        else                                                                                 \
+            k_tb<B / kQueue, TT, false><<<blocks, 256, 0, st>>>(runs, tiles, ntiles, n, par); \
+        return EMPSO_OK;                                                                     \
     }
     EMPSO_TB_CASE(20, 1) EMPSO_TB_CASE(40, 1) EMPSO_TB_CASE(80, 1) EMPSO_TB_CASE(160, 1)
     EMPSO_TB_CASE(20, 2) EMPSO_TB_CASE(40, 2) EMPSO_TB_CASE(80, 2) EMPSO_TB_CASE(160, 2)
@@ -814,10 +838,10 @@ static int enqueue_all(const Plan &pl, unsigned char *ws, int nruns, int np, int
     while (n < nt - 1) {
         int rc;
         if (n + tu.tsteps <= nt - 1) {
-            rc = launch_tb(tu.bz, tu.tsteps, runs, tiles, L.ntiles, n, par, st);
+            rc = launch_tb(tu.bz, tu.tsteps, L.iso, runs, tiles, L.ntiles, n, par, st);
             n += tu.tsteps;
         } else {
-            rc = launch_tb(kTailBz, 1, runs, tiles1, L.ntiles1, n, par, st);
+            rc = launch_tb(kTailBz, 1, L.iso, runs, tiles1, L.ntiles1, n, par, st);
             n += 1;
         }
         if (rc) return rc;
@@ -1196,10 +1220,10 @@ static int time_one(const std::vector<const empso_problem *> &pp, const std::vec
     k_zero<<<2048, 256, 0, st>>>(reinterpret_cast<float4 *>(w + L.state_off), (int64_t)(L.total - L.state_off) / 16);
     k_coef<<<dim3(512, (int)pp.size()), 256, 0, st>>>(reinterpret_cast<const CoefDesc *>(w + L.coef_off));
     for (int r = 0; r < warm; ++r)
-        if (launch_tb(tu.bz, tu.tsteps, rd, td, L.ntiles, 0, 0, st)) EMPSO_FAIL(EMPSO_ENOTSUP, "bad tuning");
+        if (launch_tb(tu.bz, tu.tsteps, L.iso, rd, td, L.ntiles, 0, 0, st)) EMPSO_FAIL(EMPSO_ENOTSUP, "bad tuning");
     EMPSO_HIP(hipEventRecord(e0, st));
     for (int r = 0; r < reps; ++r)
-        if (launch_tb(tu.bz, tu.tsteps, rd, td, L.ntiles, 0, 0, st)) EMPSO_FAIL(EMPSO_ENOTSUP, "bad tuning");
+        if (launch_tb(tu.bz, tu.tsteps, L.iso, rd, td, L.ntiles, 0, 0, st)) EMPSO_FAIL(EMPSO_ENOTSUP, "bad tuning");
     EMPSO_HIP(hipEventRecord(e1, st));
     EMPSO_HIP(hipEventSynchronize(e1));
     EMPSO_HIP(hipGetLastError());
