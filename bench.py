@@ -86,12 +86,64 @@ def cpu_baseline(geom, dt, nt, threads, steps):
             "gpt_updates_per_s": rate / 1e9, "seconds": el}
 
 
+def surrogate_report(seed=1, iters=30):
+    """Surrogate vs plain (outside the timed region): one seed of the mini
+    search, plus the network's inference on 1024 candidates and one training
+    step (batch 256) timed with HIP events."""
+    import torch
+
+    from paper_1905_12795_amd import fd, search
+    from paper_1905_12795_amd.surrogate import Surrogate
+    from workloads.configs import config, true_model
+    from workloads.models import uniform_particles
+
+    g = config("mini")
+    prob = fd.Problem(g)
+    dobs = search.observed_data(prob, true_model(g))
+    hp = search.run(g, dobs, prob, iters, "plain", seed=seed)
+    hs = search.run(g, dobs, prob, iters, "screened", seed=seed, K=16)
+    e, t = search.evals_to_reach(hs, 1.01 * hp[-1]["best"])
+    rep = {"workload": "mini: 101x301 at 10 m, 4 shots, 3x6 nodes, 32 particles, %d iterations, K = 16" % iters,
+           "seed": seed, "plain_final_misfit": hp[-1]["best"], "plain_fd_evals": hp[-1]["evaluations"],
+           "plain_wall_s": hp[-1]["wall_s"], "screened_final_misfit": hs[-1]["best"],
+           "screened_fd_evals_to_plain_final": e, "screened_wall_s_to_plain_final": t}
+    # network timings at the surrogate workload's shape (D = 60, H = 256)
+    gs = config("surrogate")
+    sur = Surrogate(gs["node_lo"], gs["node_hi"], seed=0)
+    X = uniform_particles(2048, gs["node_lo"], gs["node_hi"], 0)
+    sur.add(X, np.exp(np.random.default_rng(0).normal(5, 1, 2048)))
+    Xc = torch.tensor(uniform_particles(1024, gs["node_lo"], gs["node_hi"], 1), dtype=torch.float32, device="cuda")
+    idx = torch.arange(256, dtype=torch.int32, device="cuda")
+    for _ in range(3):
+        sur.net.predict(Xc)
+        sur.net.train_step(sur.X, sur.f, idx, sur.mu, sur.sigma, 1e-4)
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    reps = 20
+    e0.record()
+    for _ in range(reps):
+        sur.net.predict(Xc)
+    e1.record()
+    for _ in range(reps):
+        sur.net.train_step(sur.X, sur.f, idx, sur.mu, sur.sigma, 1e-4)
+    e2.record()
+    torch.cuda.synchronize()
+    D, H = sur.D, sur.net.H
+    mac = D * H + 2 * H * H + H
+    pred_ms = e0.elapsed_time(e1) / reps
+    train_ms = e1.elapsed_time(e2) / reps
+    rep.update({"predict_1024_ms": pred_ms, "predict_tflops": 2 * 1024 * mac / (pred_ms * 1e-3) / 1e12,
+                "train_step_256_ms": train_ms, "train_tflops": 3 * 2 * 256 * mac / (train_ms * 1e-3) / 1e12,
+                "bf16_mfma_peak_tflops": 2500.0})
+    return rep
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate-vs-plain report")
     ap.add_argument("--cpu-steps", type=int, default=2000)
     ap.add_argument("--bz", type=int, default=None, help="fix the tile height (default: autotune)")
     ap.add_argument("--tsteps", type=int, default=None, help="fix the temporal-blocking depth")
@@ -183,6 +235,8 @@ def main():
                      "avg_launch_us": launch_s * 1e6, "isolated_launch_us": iso_us_step * T,
                      "measured_frac": None if traffic is None else traffic / launch_s / 1e9 / HBM_PEAK_GBS},
     }
+    if not args.no_surrogate:
+        out["surrogate"] = surrogate_report()
     if not args.no_cpu_baseline:
         threads = min(16, os.cpu_count() or 1)
         out["cpu_baseline"] = cpu_baseline(g, prob.dt, prob.nt, threads, args.cpu_steps)

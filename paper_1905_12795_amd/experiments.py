@@ -1,0 +1,122 @@
+"""Measurements beyond bench.py's headline line (run on an MI355X).
+
+  python -m paper_1905_12795_amd.experiments throughput --workload batched
+      one fitness call of the three-size batch (64 particles x 16 shots),
+      autotuned; prints Gpt-updates/s and fitness evals/s.
+  python -m paper_1905_12795_amd.experiments throughput --workload full --particles 8
+      fitness of `particles` particles x 32 shots on the 601 x 1841 grid at
+      5 m (a slice of the full workload's 128-particle iteration).
+  python -m paper_1905_12795_amd.experiments surrogate --workload realistic --iters 15 --seeds 1
+      plain vs surrogate-screened vs randomly screened EMPSO on the same
+      seeds; FD evaluations and wall time until each reaches 1.01 x the plain
+      run's final best misfit.
+
+Every line printed is JSON; per-iteration search records are appended to
+--log (JSONL) as they happen.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+from paper_1905_12795_amd import fd, search  # noqa: E402
+from workloads.configs import config, true_model  # noqa: E402
+from workloads.models import uniform_particles  # noqa: E402
+
+
+def _emit(d):
+    print(json.dumps(d), flush=True)
+
+
+def throughput(workload, particles, calls):
+    if workload == "batched":
+        geoms = config("batched")
+        probs = [fd.Problem(g) for g in geoms]
+        npart = particles or geoms[0]["particles"]
+        pop = [p % 3 for p in range(npart)]
+        lo, hi = geoms[0]["node_lo"], geoms[0]["node_hi"]
+        seed = geoms[0]["particle_seed"]
+    else:
+        g = config(workload)
+        geoms = [g]
+        probs = [fd.Problem(g)]
+        npart = particles or g["particles"]
+        pop = [0] * npart
+        lo, hi = g["node_lo"], g["node_hi"]
+        seed = g["particle_seed"]
+    t0 = time.perf_counter()
+    obs = [search.observed_data(p, true_model(g)) for p, g in zip(probs, geoms)]
+    torch.cuda.synchronize()
+    _emit({"stage": "observed data", "seconds": time.perf_counter() - t0})
+    X = uniform_particles(npart, lo, hi, seed)
+    fb = fd.FitnessBatch(probs, obs, pop)
+    best, us = fb.autotune(X)
+    _emit({"stage": "autotuned", "tuning": best, "us_per_step": us})
+    fb(X)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(calls):
+        t0 = time.perf_counter()
+        f = fb(X)
+        f.cpu()
+        times.append(time.perf_counter() - t0)
+        _emit({"stage": "call", "seconds": times[-1]})
+    s = float(np.median(times))
+    _emit({"workload": workload, "particles": npart, "runs": int(sum(probs[q].nshots for q in pop)),
+           "updates_per_call": fb.updates, "seconds_per_call": s, "gpt_updates_per_s": fb.updates / s / 1e9,
+           "fitness_evals_per_s": npart / s, "tuning": best,
+           "grids": [[p.info.Nz, p.info.Nx] for p in probs], "nt": probs[0].nt})
+
+
+def surrogate(workload, iters, seeds, K, log):
+    g = config(workload)
+    if workload == "realistic":
+        g = dict(g)
+        g["particles"] = config("surrogate")["particles"]      # 64 particles x K = 16 -> 1024 candidates
+    prob = fd.Problem(g)
+    dobs = search.observed_data(prob, true_model(g))
+    for seed in seeds:
+        res = {"workload": workload, "seed": seed, "particles": g["particles"], "K": K, "iterations": iters}
+        hp = search.run(g, dobs, prob, iters, "plain", seed=seed, log_path=log)
+        target = 1.01 * hp[-1]["best"]
+        res.update(plain_final=hp[-1]["best"], plain_evals=hp[-1]["evaluations"], plain_wall=hp[-1]["wall_s"])
+        for mode in ("screened", "random"):
+            h = search.run(g, dobs, prob, iters, mode, seed=seed, K=K, log_path=log)
+            e, t = search.evals_to_reach(h, target)
+            res.update({mode + "_final": h[-1]["best"], mode + "_evals_to_plain": e, mode + "_wall_to_plain": t})
+            if mode == "screened":
+                rh = [r["surrogate_rho"] for r in h if "surrogate_rho" in r]
+                res["screened_mean_rho"] = float(np.mean(rh)) if rh else None
+        _emit(res)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    t = sub.add_parser("throughput")
+    t.add_argument("--workload", default="batched", choices=["tiny", "realistic", "batched", "full"])
+    t.add_argument("--particles", type=int, default=0)
+    t.add_argument("--calls", type=int, default=3)
+    s = sub.add_parser("surrogate")
+    s.add_argument("--workload", default="mini", choices=["mini", "realistic"])
+    s.add_argument("--iters", type=int, default=30)
+    s.add_argument("--seeds", default="1,2,3")
+    s.add_argument("--K", type=int, default=16)
+    s.add_argument("--log", default=None)
+    a = ap.parse_args()
+    if a.cmd == "throughput":
+        throughput(a.workload, a.particles, a.calls)
+    else:
+        surrogate(a.workload, a.iters, [int(x) for x in a.seeds.split(",")], a.K, a.log)
+
+
+if __name__ == "__main__":
+    main()
