@@ -21,10 +21,11 @@
  *     down; the origin is the top-left corner. The padded grid adds nbl points
  *     of absorbing layer on every side; beyond it the field is zero.
  *   - Scheme, with m = 1/v^2, damping d and a = d*dt/2:
- *       u^{n+1} = u^n + delta^{n+1},
- *       delta^{n+1} = [ (1-a) delta^n + (v dt)^2 (Lap_h u^n + f^n) ] / (1+a),
+ *       u^{n+1} = u^n + delta,
+ *       delta = [ (1-a) (u^n - u^{n-1}) + (v dt)^2 (Lap_h u^n + f^n) ] / (1+a),
  *     which is the centred scheme u^{n+1} = [2u^n - (1-a)u^{n-1} + (v dt)^2
- *     (Lap_h u^n + f^n)]/(1+a) carried in increment form for FP32 accuracy.
+ *     (Lap_h u^n + f^n)]/(1+a) evaluated in increment form for FP32 accuracy
+ *     (the increment u^n - u^{n-1} is formed before anything is added to it).
  *     Lap_h uses the eighth-order central weights (-205/72, 8/5, -1/5, 8/315,
  *     -1/560). u^0 = u^{-1} = 0.
  *   - Damping: d = d0 (l/nbl)^2 per axis, d0 = 3 vmax ln(1/R)/(2 nbl h), with l
@@ -105,7 +106,7 @@ typedef struct {
 typedef struct {
     int32_t variant;         /* reserved, 0                                             */
     int32_t bz;              /* output rows per tile: 20, 40, 80 or 160                  */
-    int32_t tsteps;          /* time steps per launch (temporal-blocking depth): 1..3   */
+    int32_t tsteps;          /* time steps per launch (temporal-blocking depth): 1..4   */
     int32_t prefetch;        /* rows of u requested ahead of use: 1                     */
     int32_t use_graph;       /* 1: replay the time loop from a captured HIP graph       */
 } empso_tuning;

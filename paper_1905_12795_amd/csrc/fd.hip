@@ -8,30 +8,32 @@
 // control-node velocities reach the FD grid by bilinear interpolation.
 //
 // Layout in HBM (per run = one particle x one shot):
-//   three FP32 fields u_even, u_odd, delta, each (Nz + 8) rows x S floats,
-//   x fastest. Row s holds padded row I = s - 4 and column c holds padded
-//   column J = c - 4; the 4-deep ring around the padded grid and the row tail
-//   up to the stride S (a multiple of 64 floats, S >= Nx + 8) stay zero, so
-//   the stencil needs no bounds tests. The coefficient field C = (v dt)^2 of a
-//   particle uses the same layout and is shared by all of its shots.
-// Step n -> n+1 reads u^n from the buffer of parity n and writes u^{n+1} to
-// the other one; delta is updated in place.
+//   two ping-pong pairs of FP32 fields (u_0, v_0) and (u_1, v_1), each field
+//   (Nz + 32) rows x S floats, x fastest, the four fields contiguous. A pair
+//   holds two consecutive time levels, u^n in u_p and u^{n-1} in v_p. Row s
+//   holds padded row I = s - 16 and column c holds padded column J = c - 16;
+//   the 16-deep ring around the padded grid and the row tail up to the stride
+//   S (a multiple of 64 floats, S >= Nx + 32) stay zero, so the stencil needs
+//   no bounds tests. The coefficient field C = (v dt)^2 of a particle uses the
+//   same layout and is shared by all of its shots.
+// A launch advances every run by T time steps (temporal blocking): it reads
+// the pair of parity par and writes the other one.
 //
 // Kernel shape: one 64-lane wavefront owns a tile of 256 columns (4 adjacent
 // columns per lane, 16-byte loads) by bz rows and marches down the rows,
-// keeping the 9 rows of its z-stencil in registers; x-neighbours come from the
-// adjacent lanes by cross-lane permutes, the two tile-edge lanes fetch the
-// 4-column halos. Damping, source injection and receiver residuals are fused
-// into the same pass. Tiles are ordered particle, z-strip, x-strip, shot
-// (shot fastest) so that the shots of a particle read the shared coefficient
-// tile back to back from L2, and block indices are remapped so that
-// consecutive tiles run on the same XCD.
+// keeping the 9 rows of each level's z-stencil in registers; x-neighbours
+// come from the adjacent lanes by DPP lane shifts. Damping, source injection
+// and receiver residuals are fused into the same pass. Tiles are ordered
+// particle, z-strip, x-strip, shot (shot fastest) so that the shots of a
+// particle read the shared coefficient tile back to back from L2, and block
+// indices are remapped so that consecutive tiles run on the same XCD.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <mutex>
+#include <type_traits>
 #include <unordered_map>
 #include <vector>
 
@@ -64,7 +66,7 @@ static const int kLanesX = 64;     // lanes per wavefront
 static const int kColsPerLane = 4;
 static const int kTileX = kLanesX * kColsPerLane;   // columns loaded by one wavefront
 static const int kQueue = 10;      // row-queue slots per level (9 stencil rows + 1 prefetch)
-static const int kMaxT = 3;        // deepest temporal blocking (4 kMaxT <= kRing)
+static const int kMaxT = 4;        // deepest temporal blocking (4 kMaxT <= kRing)
 
 }  // namespace empso
 
@@ -79,6 +81,7 @@ struct empso_problem {
     int D;                     // ncz * ncx
     std::vector<int> srcI, srcJ;   // padded indices per shot
     int recI;                  // padded receiver row
+    int zlo, zhi;              // stored rows [zlo, zhi) are undamped along z (a_z = 0)
     std::vector<int> reccol;   // padded column of each receiver
     float *d_wav = nullptr;    // [nt]
     float *d_az = nullptr;     // [Nz] a = d dt / 2 along z
@@ -223,6 +226,12 @@ extern "C" int empso_problem_create(const empso_geometry *gp, empso_problem **ou
             ax[J] = (float)(0.5 * g.dt * d0x * r * r);
         }
     }
+    p->zlo = p->zhi = 0;
+    for (int I = 0; I < p->Nz; ++I) {
+        if (az[I] != 0.f) continue;
+        if (p->zhi == 0) p->zlo = I + kRing;
+        p->zhi = I + 1 + kRing;
+    }
     const double idz2 = 1.0 / (g.dz * g.dz), idx2 = 1.0 / (g.dx * g.dx);
     p->c0 = (float)(kW[0] * (idz2 + idx2));
     for (int k = 0; k < 4; ++k) {
@@ -274,7 +283,7 @@ extern "C" int empso_default_tuning(empso_tuning *t) {
     if (!t) EMPSO_FAIL(EMPSO_EINVAL, "NULL argument");
     t->variant = 0;
     t->bz = 160;
-    t->tsteps = 3;
+    t->tsteps = 4;
     t->prefetch = 1;
     t->use_graph = 1;
     return EMPSO_OK;
@@ -284,7 +293,7 @@ extern "C" int empso_default_tuning(empso_tuning *t) {
 // Device-side descriptors
 // ---------------------------------------------------------------------------
 struct RunDesc {
-    float *u[2], *d[2];         // ping-pong fields u and delta (storage base, ring included)
+    float *u[2], *v[2];         // ping-pong pairs (u^n, u^{n-1}) (storage base, ring included)
     const float *C;             // coefficient field of the particle
     const float *obs;           // [nt][nrec] observed traces of this shot (fitness mode)
     float *traces;              // [nt][nrec] output (record mode) or NULL
@@ -292,7 +301,8 @@ struct RunDesc {
     const float *wav, *az, *ax;
     const int *recmap, *reccol;
     int Nz, Nx, S, nrec, recS, srcS, srcC, nt;
-    unsigned fbytes;            // bytes of one stored field (u, delta or C)
+    int zlo, zhi;               // stored rows [zlo, zhi) have a_z = 0
+    unsigned fbytes;            // bytes of one stored field (u, v or C)
     float c0, cz1, cz2, cz3, cz4, cx1, cx2, cx3, cx4, wscale;
 };
 
@@ -434,51 +444,60 @@ __device__ __forceinline__ float from_lane_above(float v) {
 
 // T time steps n -> n+T for every tile, all levels in registers.
 //
+// Fields: each run stores two time levels of u, u^n and u^{n-1}, in two
+// ping-pong pairs. The update is the increment form with the increment
+// rebuilt from them: dp = u^n - u^{n-1} (a difference of two stored FP32
+// values, exact up to one rounding of itself), then
+//   d = (C (lap u^n + f^n) + (1 - a) dp) / (1 + a),   u^{n+1} = u^n + d.
+// Level t needs u^{n+t-2} at its row, which is the oldest row of level t-1's
+// input queue, so no increments are carried between levels.
+//
 // A wavefront loads 256 columns (4 per lane) and owns the central 256 - 8T of
 // them: the level-t result is exact 4t columns in from either edge, so
 // neighbouring tiles overlap by 8T columns and recompute them. In z, the
 // wavefront owns M * 10 rows and marches down from 4T rows above them. In
 // each step of the march, level 1 updates row r from u^n rows r-4 .. r+4 (a
-// queue of 10 slots with one row requested ahead) and delta^n(r); level t
+// queue of 10 slots with one row requested ahead) and u^{n-1}(r); level t
 // updates row r - 4(t-1) from the 9-row queue of level t-1's results and the
-// delta that level t-1 produced for that row 4 steps earlier (a 5-slot queue).
-// Level T writes u^{n+T} and delta^{n+T} for owned rows and columns; every
-// other store gets an out-of-range buffer offset and is dropped by the
-// hardware, so the loop body has no branches. Rows above or below the stored
-// field read as zero for the same reason.
+// oldest row of level t-1's own queue. Level T writes u^{n+T} and u^{n+T-1}
+// for owned rows and columns; every other store gets an out-of-range buffer
+// offset and is dropped by the hardware, so the loop body has no branches.
+// Rows above or below the stored field read as zero for the same reason.
 // Points outside the padded grid need no masking: C is zero there and so are
-// the incoming u and delta, so they stay exactly zero at every level.
-// Receiver samples of each level (u^{n+t-1} on the receiver row) are kept in
-// registers and accumulated after the march by the owning lanes.
+// the incoming fields, so they stay exactly zero at every level.
+// Receiver samples of each level (u^{n+t-1} on the receiver row) are parked
+// in LDS and accumulated after the march by the owning lanes.
 template <int M, int T, bool ISO>
-__global__ __launch_bounds__(256) void k_tb(const RunDesc *__restrict__ runs, const int4 *__restrict__ tiles,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(T < 3 ? 3 : 2))) void k_tb(const RunDesc *__restrict__ runs, const int4 *__restrict__ tiles,
                                             int ntiles, int n, int par) {
     constexpr int NS = kQueue;
-    constexpr int ND = 5;
     constexpr int BZ = M * NS;
     constexpr int FILL = 8 * (T - 1);               // march steps before the first owned row
     constexpr int TQ = T > 1 ? T - 1 : 1;
+    __shared__ float4 srec[4][T][64];
     const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
-    const int tix = __builtin_amdgcn_readfirstlane(lb * 4 + (int)(threadIdx.x >> 6));
+    const int wv = (int)(threadIdx.x >> 6);
+    const int tix = __builtin_amdgcn_readfirstlane(lb * 4 + wv);
     if (tix >= ntiles) return;
     const int lane = threadIdx.x & 63;
     const int4 t = tiles[tix];
     const RunDesc R = runs[t.x];
     const int S = R.S;
     const int bot = R.Nz + kRing;                   // end of the stored rows of the padded grid
-    // One buffer resource spans the run's four contiguous fields u0 | u1 | d0 | d1;
-    // the byte offsets below select the input and output buffers (selects,
-    // not R.u[par]: a runtime index would move R to scratch memory). Reads
-    // that run past a field land in the next field's zero ring or beyond the
-    // range (zero); both only feed rows that are never stored.
+    // One buffer resource spans the run's four contiguous fields
+    // u0 | u1 | v0 | v1 (pair p = u_p, v_p holds u^n, u^{n-1}); the byte
+    // offsets below select the input and output pairs (selects, not
+    // R.u[par]: a runtime index would move R to scratch memory). Reads that
+    // run past a field land in the next field's zero ring or beyond the range
+    // (zero); both only feed rows that are never stored.
     const rsrc_t F = make_rsrc(R.u[0], 4u * R.fbytes);
     const int fb = (int)R.fbytes;
-    const int uin = par ? fb : 0, din = par ? 3 * fb : 2 * fb;
-    const int uout = par ? 0 : fb, dout = par ? 2 * fb : 3 * fb;
+    const int uin = par ? fb : 0, vin = par ? 3 * fb : 2 * fb;
+    const int uout = par ? 0 : fb, vout = par ? 2 * fb : 3 * fb;
     const rsrc_t Cf = make_rsrc(R.C, R.fbytes);
     const int c = t.z + 4 * lane;                   // stored column of this lane's first element
     // Lanes past the stored row work on its last four columns instead: that
-    // tail is zero in u, delta and C, the lanes compute zeros there and any
+    // tail is zero in every field, the lanes compute zeros there and any
     // store they make writes zeros into the tail, which keeps it zero.
     const int cc = min(c, S - 4);                   // past the row: its zero tail
     const int J0 = c - kRing;
@@ -503,31 +522,26 @@ __global__ __launch_bounds__(256) void k_tb(const RunDesc *__restrict__ runs, co
     for (int l = 0; l < T; ++l) fsrc[l] = sld(R.wav + min(n + l, R.nt - 1)) * R.wscale;
 
     const int rs = s0 - 4 * (T - 1);                // level-1 row of the first march step
-    float4 q0[NS], qu[TQ][NS], qd[TQ][ND], dq[2], cq[T][2], rec[T];
+    float4 q0[NS], qu[TQ][NS], vq, cq[T];
 #pragma unroll
     for (int j = 0; j < 9; ++j) q0[j] = bld4(F, uin + (rs - 4 + j) * rowb + lcol);
-    dq[0] = bld4(F, din + rs * rowb + lcol);
+    vq = bld4(F, vin + rs * rowb + lcol);
 #pragma unroll
-    for (int l = 0; l < T; ++l) {
-        cq[l][0] = bld4(Cf, (rs - 4 * l) * rowb + lcol);
-        rec[l] = make_float4(0.f, 0.f, 0.f, 0.f);
-    }
+    for (int l = 0; l < T; ++l) cq[l] = bld4(Cf, (rs - 4 * l) * rowb + lcol);
     // the level queues fill during the first march steps; start them at zero
 #pragma unroll
     for (int l = 0; l < TQ; ++l) {
 #pragma unroll
         for (int j = 0; j < NS; ++j) qu[l][j] = make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll
-        for (int j = 0; j < ND; ++j) qd[l][j] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
 
-    // One march step: k = (step index) mod 10, known at compile time.
-    auto step = [&](const int k, const int r1) {
+    // One march step: k = (step index) mod 10, known at compile time. The
+    // damped form is taken for the whole step when any of its T rows, or the
+    // tile, lies in the absorbing layer.
+    auto step = [&](const int k, const int r1, auto damp_tag) __attribute__((always_inline)) {
+        constexpr bool damped = decltype(damp_tag)::value;
         q0[(k + 9) % NS] = bld4(F, uin + (r1 + 5) * rowb + lcol);
-        dq[(k + 1) & 1] = bld4(F, din + (r1 + 1) * rowb + lcol);
-#pragma unroll
-        for (int l = 0; l < T; ++l) cq[l][(k + 1) & 1] = bld4(Cf, (r1 + 1 - 4 * l) * rowb + lcol);
-        float4 un = make_float4(0.f, 0.f, 0.f, 0.f), dn = un;
+        float4 un = make_float4(0.f, 0.f, 0.f, 0.f), ue = un;
 #pragma unroll
         for (int l = 0; l < T; ++l) {
             const float4 *src = (l == 0) ? q0 : qu[l > 0 ? l - 1 : 0];
@@ -536,9 +550,14 @@ __global__ __launch_bounds__(256) void k_tb(const RunDesc *__restrict__ runs, co
             const float4 p2 = src[(k + 2) % NS], m2 = src[(k + 6) % NS];
             const float4 p3 = src[(k + 1) % NS], m3 = src[(k + 7) % NS];
             const float4 p4 = src[(k + 0) % NS], m4 = src[(k + 8) % NS];
-            const float4 d4 = (l == 0) ? dq[k & 1] : qd[l > 0 ? l - 1 : 0][(k + 1) % ND];
-            const float4 C4 = cq[l][k & 1];
+            // u^{n+l-1} at this level's row: loaded for level 1, else the
+            // oldest row of the level below's queue
+            const float4 pv = (l == 0) ? vq : ((l == 1) ? q0 : qu[l > 1 ? l - 2 : 0])[k % NS];
+            const float4 C4 = cq[l];
             const int r = r1 - 4 * l;
+            // next step's operands of this level, requested once these are read
+            cq[l] = bld4(Cf, (r + 1) * rowb + lcol);
+            if (l == 0) vq = bld4(F, vin + (r1 + 1) * rowb + lcol);
             const float v[12] = {from_lane_below(ce.x), from_lane_below(ce.y),
                                  from_lane_below(ce.z), from_lane_below(ce.w),
                                  ce.x, ce.y, ce.z, ce.w,
@@ -548,12 +567,11 @@ __global__ __launch_bounds__(256) void k_tb(const RunDesc *__restrict__ runs, co
             const float pz2[4] = {p2.x, p2.y, p2.z, p2.w}, mz2[4] = {m2.x, m2.y, m2.z, m2.w};
             const float pz3[4] = {p3.x, p3.y, p3.z, p3.w}, mz3[4] = {m3.x, m3.y, m3.z, m3.w};
             const float pz4[4] = {p4.x, p4.y, p4.z, p4.w}, mz4[4] = {m4.x, m4.y, m4.z, m4.w};
-            const float dv[4] = {d4.x, d4.y, d4.z, d4.w};
+            const float pvv[4] = {pv.x, pv.y, pv.z, pv.w};
             const float Cv[4] = {C4.x, C4.y, C4.z, C4.w};
-            const float azr = sld(R.az + min(max(r - kRing, 0), R.Nz - 1));
-            const bool damped = tile_xdamp || (azr != 0.0f);
+            const float azr = damped ? sld(R.az + min(max(r - kRing, 0), R.Nz - 1)) : 0.0f;
             const float fs = (r == R.srcS) ? fsrc[l] : 0.0f;   // wave-uniform
-            float uo[4], dd[4];
+            float uo[4];
 #pragma unroll
             for (int k2 = 0; k2 < 4; ++k2) {
                 const float u = v[4 + k2];
@@ -579,44 +597,45 @@ __global__ __launch_bounds__(256) void k_tb(const RunDesc *__restrict__ runs, co
                     lap = fmaf(R.cx1, fmaf(-2.0f, u, v[3 + k2] + v[5 + k2]), lap);
                 }
                 lap = fmaf(srcm[k2], fs, lap);
+                const float dp = u - pvv[k2];
                 // The damped form reduces bit for bit to the undamped one
-                // when a = 0 ((1-a) dv = dv, rcp(1) = 1), so a point's result
+                // when a = 0 ((1-a) dp = dp, rcp(1) = 1), so a point's result
                 // does not depend on which branch its tile takes.
                 float d;
-                if (damped) {
+                if constexpr (damped) {
                     const float a = azr + axk[k2];
                     const float inv = __builtin_amdgcn_rcpf(1.0f + a);
-                    d = fmaf(Cv[k2], lap, (1.0f - a) * dv[k2]) * inv;
+                    d = fmaf(Cv[k2], lap, (1.0f - a) * dp) * inv;
                 } else {
-                    d = fmaf(Cv[k2], lap, dv[k2]);
+                    d = fmaf(Cv[k2], lap, dp);
                 }
-                dd[k2] = d;
                 uo[k2] = u + d;
             }
-            if (r == R.recS) rec[l] = ce;
+            if (r == R.recS) srec[wv][l][lane] = ce;
             un = make_float4(uo[0], uo[1], uo[2], uo[3]);
-            dn = make_float4(dd[0], dd[1], dd[2], dd[3]);
-            if (l < T - 1) {
-                qu[l][(k + 8) % NS] = un;
-                qd[l][k % ND] = dn;
-            }
+            ue = ce;
+            if (l < T - 1) qu[l][(k + 8) % NS] = un;
         }
         const int rT = r1 - 4 * (T - 1);
         const bool ok = own && (rT >= s0) && (rT < s1);
         const int o = rT * rowb + lcol;
         bst4(F, ok ? uout + o : kDrop, un);            // kDrop: dropped by the range check
-        bst4(F, ok ? dout + o : kDrop, dn);
+        bst4(F, ok ? vout + o : kDrop, ue);
     };
 
-    // fill: the first 8(T-1) steps produce no owned output yet
-#pragma unroll
-    for (int j = 0; j < FILL; ++j) step(j % NS, rs + j);
-    // steady march in blocks of NS steps (the last block may run past the
-    // tile; those stores are dropped)
+    auto step_any = [&](const int k, const int r1) __attribute__((always_inline)) {
+        if (tile_xdamp || r1 - 4 * (T - 1) < R.zlo || r1 >= R.zhi)
+            step(k, r1, std::true_type{});
+        else
+            step(k, r1, std::false_type{});
+    };
+    // march in blocks of NS steps: the first 8(T-1) steps only fill the
+    // level queues and the last block may run past the tile; the stores of
+    // those steps are dropped
     const int nit = FILL + (s1 - s0);
-    for (int j = FILL; j < nit; j += NS) {
+    for (int j = 0; j < nit; j += NS) {
 #pragma unroll
-        for (int kk = 0; kk < NS; ++kk) step((FILL + kk) % NS, rs + j + kk);
+        for (int kk = 0; kk < NS; ++kk) step_any(kk, rs + j + kk);
     }
     if (R.recS >= s0 && R.recS < s1 && own) {
         // reload the descriptor (the receiver tables need not stay live in
@@ -624,7 +643,7 @@ __global__ __launch_bounds__(256) void k_tb(const RunDesc *__restrict__ runs, co
         const RunDesc *Rp = runs + t.x;
         asm volatile("" : "+s"(Rp));
 #pragma unroll
-        for (int l = 0; l < T; ++l) sample_receivers(*Rp, n + l, J0, rec[l]);
+        for (int l = 0; l < T; ++l) sample_receivers(*Rp, n + l, J0, srec[wv][l][lane]);
     }
 }
 
@@ -818,6 +837,7 @@ static int launch_tb(int bz, int T, bool iso, const RunDesc *runs, const int4 *t
     EMPSO_TB_CASE(20, 1) EMPSO_TB_CASE(40, 1) EMPSO_TB_CASE(80, 1) EMPSO_TB_CASE(160, 1)
     EMPSO_TB_CASE(20, 2) EMPSO_TB_CASE(40, 2) EMPSO_TB_CASE(80, 2) EMPSO_TB_CASE(160, 2)
     EMPSO_TB_CASE(20, 3) EMPSO_TB_CASE(40, 3) EMPSO_TB_CASE(80, 3) EMPSO_TB_CASE(160, 3)
+    EMPSO_TB_CASE(20, 4) EMPSO_TB_CASE(40, 4) EMPSO_TB_CASE(80, 4) EMPSO_TB_CASE(160, 4)
 #undef EMPSO_TB_CASE
     return EMPSO_ENOTSUP;
 }
@@ -905,13 +925,14 @@ static void build_header(Plan &pl, unsigned char *ws, const std::vector<const em
         RunDesc &d = rd[r];
         float *f = reinterpret_cast<float *>(ws + L.field_of_run[r]);
         const size_t fe = field_bytes(p) / sizeof(float);
-        d.u[0] = f; d.u[1] = f + fe; d.d[0] = f + 2 * fe; d.d[1] = f + 3 * fe;
+        d.u[0] = f; d.u[1] = f + fe; d.v[0] = f + 2 * fe; d.v[1] = f + 3 * fe;
         d.C = reinterpret_cast<const float *>(ws + L.C_of_particle[rs.particle]);
         d.obs = rs.obs; d.traces = rs.traces;
         d.acc = reinterpret_cast<double *>(ws + L.acc_of_run[r]);
         d.wav = p->d_wav; d.az = p->d_az; d.ax = p->d_ax; d.recmap = p->d_recmap; d.reccol = p->d_reccol;
         d.Nz = p->Nz; d.Nx = p->Nx; d.S = p->S; d.nrec = p->g.nrec;
         d.recS = p->recI + kRing;
+        d.zlo = p->zlo; d.zhi = p->zhi;
         d.srcS = p->srcI[rs.shot] + kRing;
         d.srcC = p->srcJ[rs.shot] + kRing;
         d.nt = p->g.nt;

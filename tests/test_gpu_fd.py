@@ -126,7 +126,8 @@ def test_multi_tile_ragged_traces_and_fitness(gfd):
     fo, _ = ofd.fitness_batch(op, X.astype(np.float32).astype(np.float64), dobs)
     fb = gfd.FitnessBatch([gp], [torch.tensor(dobs, device="cuda")], [0] * 5)
     n2 = float(np.sum(dobs.astype(np.float64) ** 2))
-    for t in (dict(bz=20, T=1, use_graph=0), dict(bz=40, T=2, use_graph=1), dict(bz=80, T=3, use_graph=1)):
+    for t in (dict(bz=20, T=1, use_graph=0), dict(bz=40, T=2, use_graph=1), dict(bz=80, T=3, use_graph=1),
+              dict(bz=160, T=4, use_graph=1)):
         tu = gfd.default_tuning()
         tu.bz, tu.tsteps, tu.use_graph = t["bz"], t["T"], t["use_graph"]
         fg = fb(X, tuning=tu).cpu().numpy().astype(np.float64)
@@ -143,7 +144,7 @@ def test_tiling_graph_and_repeat_are_bitwise_invariant(gfd):
     fb = gfd.FitnessBatch([gp], [dobs], [0] * 7)
     outs = []
     for bz in (20, 40, 80, 160):
-        for T in (1, 2, 3):
+        for T in (1, 2, 3, 4):
             for graph in (0, 1):
                 tu = gfd.default_tuning()
                 tu.bz, tu.tsteps, tu.use_graph = bz, T, graph
@@ -166,7 +167,7 @@ def test_wide_grid_interior_tiles_bitwise_invariant(gfd):
     fb = gfd.FitnessBatch([gp], [dobs], [0] * 3)
     ref = None
     for bz in (20, 80, 160):
-        for T in (1, 2, 3):
+        for T in (1, 2, 3, 4):
             tu = gfd.default_tuning()
             tu.bz, tu.tsteps = bz, T
             got = fb(X, tuning=tu).clone()
@@ -184,7 +185,7 @@ def test_temporal_blocking_traces_bitwise_equal_single_step(gfd):
                       dtype=torch.float32, device="cuda")
     ref = gfd.forward_shots(gp, vp).cpu()
     assert torch.isfinite(ref).all() and ref.abs().max() > 0
-    for T in (2, 3):
+    for T in (2, 3, 4):
         tu = gfd.default_tuning()
         tu.tsteps = T
         got = gfd.forward_shots(gp, vp, tuning=tu).cpu()
@@ -241,7 +242,7 @@ def test_autotuner_picks_a_valid_tuning_with_identical_results(gfd):
     fb = gfd.FitnessBatch([gp], [dobs], [0] * 4)
     ref = fb(X).clone()
     best, us = fb.autotune(X)
-    assert best["bz"] in (20, 40, 80, 160) and 1 <= best["tsteps"] <= 3 and best["use_graph"] == 1
+    assert best["bz"] in (20, 40, 80, 160) and 1 <= best["tsteps"] <= 4 and best["use_graph"] == 1
     assert us > 0
     assert fb.time_tuning(X, fb.tuning, reps=2) > 0
     assert torch.equal(fb(X), ref)
