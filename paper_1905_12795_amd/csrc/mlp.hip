@@ -101,25 +101,28 @@ struct Gemm {
 
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef short s8v __attribute__((ext_vector_type(8)));
-typedef float f16v __attribute__((ext_vector_type(16)));
+typedef float f4v __attribute__((ext_vector_type(4)));
 
-// C = A * B with one 64-lane wavefront per 32x32 output tile and
-// v_mfma_f32_32x32x16_bf16 (K = 16 per instruction). Operand lanes: lane i
-// supplies A row (i mod 32), B column (i mod 32), and K elements
-// 8*(i div 32) .. +7 of the 16-wide K slice. Result: lane i holds column
-// (i mod 32), rows 8*(j div 4) + 4*(i div 32) + (j mod 4) for j = 0..15.
+// C = A * B with one 64-lane wavefront per 16x16 output tile and
+// v_mfma_f32_16x16x32_bf16 (K = 32 per instruction): the small batches of the
+// surrogate give few output tiles, so small tiles keep more wavefronts busy.
+// Operand lanes: lane i supplies A row (i mod 16), B column (i mod 16), and
+// the same 8 K indices 8*(i div 16) .. +7 of the 32-wide K slice for both
+// operands (the product does not depend on how the instruction orders K
+// internally, only on A and B using the same assignment). Result: lane i
+// holds column (i mod 16), rows 4*(i div 16) + j for j = 0..3.
 // Out-of-range rows, columns and K elements are read as zero.
 __global__ __launch_bounds__(256) void k_gemm(const Gemm g) {
     const int lane = threadIdx.x & 63;
-    const int tilesN = (g.N + 31) / 32;
+    const int tilesN = (g.N + 15) / 16;
     const int tile = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int tilesM = (g.M + 31) / 32;
+    const int tilesM = (g.M + 15) / 16;
     if (tile >= tilesM * tilesN) return;
-    const int m0 = (tile / tilesN) * 32, n0 = (tile % tilesN) * 32;
-    const int r = lane & 31, kh = (lane >> 5) * 8;
+    const int m0 = (tile / tilesN) * 16, n0 = (tile % tilesN) * 16;
+    const int r = lane & 15, kh = (lane >> 4) * 8;
     const int am = m0 + r, bn = n0 + r;
-    f16v acc = {};
-    for (int k0 = 0; k0 < g.K; k0 += 16) {
+    f4v acc = {};
+    for (int k0 = 0; k0 < g.K; k0 += 32) {
         s8v a, b;
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
@@ -127,14 +130,14 @@ __global__ __launch_bounds__(256) void k_gemm(const Gemm g) {
             a[e] = (am < g.M && k < g.K) ? (short)g.A[(size_t)am * g.sam + (size_t)k * g.sak] : (short)0;
             b[e] = (bn < g.N && k < g.K) ? (short)g.B[(size_t)k * g.sbk + (size_t)bn * g.sbn] : (short)0;
         }
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf8, a), __builtin_bit_cast(bf8, b), acc,
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a), __builtin_bit_cast(bf8, b), acc,
                                                       0, 0, 0);
     }
     const int col = n0 + r;
     if (col >= g.N) return;
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-        const int row = m0 + 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3);
+    for (int j = 0; j < 4; ++j) {
+        const int row = m0 + 4 * (lane >> 4) + j;
         if (row >= g.M) continue;
         const size_t o = (size_t)row * g.N + col;
         const float v = acc[j];
@@ -165,13 +168,23 @@ __global__ void k_mlp_input(const float *__restrict__ X, const int *__restrict__
 }
 
 // y[m] = w4 . h3[m] + b4 (FP32 accumulation in a fixed order).
-__global__ void k_head_fwd(const uint16_t *__restrict__ H3, const float *__restrict__ w4, const float *__restrict__ b4,
-                           int n, int H, float *__restrict__ y) {
-    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+// Sum over the 64 lanes of a wavefront (butterfly: every lane gets the same bits).
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// y[m] = w4 . h3[m] + b4, one wavefront per row.
+__global__ __launch_bounds__(256) void k_head_fwd(const uint16_t *__restrict__ H3, const float *__restrict__ w4,
+                                                  const float *__restrict__ b4, int n, int H, float *__restrict__ y) {
+    const int m = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     if (m >= n) return;
     float s = 0.0f;
-    for (int h = 0; h < H; ++h) s = fmaf(w4[h], bf2f(H3[(size_t)m * H + h]), s);
-    y[m] = s + b4[0];
+    for (int h = lane; h < H; h += 64) s = fmaf(w4[h], bf2f(H3[(size_t)m * H + h]), s);
+    s = wave_sum(s);
+    if (lane == 0) y[m] = s + b4[0];
 }
 
 // Targets from the evaluated fitness: t = (log(max(f, tiny)) - mu)/sigma.
@@ -199,39 +212,47 @@ __global__ __launch_bounds__(256) void k_loss(const float *__restrict__ y, const
 
 // Head backward: dw4[h] = sum_m dy[m] h3[m][h], db4 = sum_m dy[m],
 // dz3[m][h] = dy[m] w4[h] GELU'(z3[m][h]).
-__global__ void k_head_bwd(const float *__restrict__ dy, const uint16_t *__restrict__ H3, const float *__restrict__ Z3,
-                           const float *__restrict__ w4, int n, int H, float *__restrict__ gw4, float *__restrict__ gb4,
-                           float *__restrict__ dZ3, uint16_t *__restrict__ dZ3b) {
-    const int h = blockIdx.x * blockDim.x + threadIdx.x;
-    if (h < H) {
-        float s = 0.0f;
-        for (int m = 0; m < n; ++m) s = fmaf(dy[m], bf2f(H3[(size_t)m * H + h]), s);
-        gw4[h] = s;
-        if (h == 0) {
-            float sb = 0.0f;
-            for (int m = 0; m < n; ++m) sb += dy[m];
-            gb4[0] = sb;
-        }
-        for (int m = 0; m < n; ++m) {
-            const size_t o = (size_t)m * H + h;
-            const float dz = dy[m] * w4[h] * gelu_grad(Z3[o]);
-            dZ3[o] = dz;
-            dZ3b[o] = f2bf(dz);
-        }
+// dZ3[m][h] = dy[m] w4[h] GELU'(Z3[m][h]) (FP32 and BF16 copies).
+__global__ __launch_bounds__(256) void k_head_dz(const float *__restrict__ dy, const float *__restrict__ Z3,
+                                                 const float *__restrict__ w4, int n, int H, float *__restrict__ dZ3,
+                                                 uint16_t *__restrict__ dZ3b) {
+    const int64_t total = (int64_t)n * H;
+    for (int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; o < total; o += (int64_t)gridDim.x * blockDim.x) {
+        const int m = (int)(o / H), h = (int)(o - (int64_t)m * H);
+        const float dz = dy[m] * w4[h] * gelu_grad(Z3[o]);
+        dZ3[o] = dz;
+        dZ3b[o] = f2bf(dz);
     }
 }
 
-// db[h] = sum_m dZ[m][h] in row order.
-__global__ void k_colsum(const float *__restrict__ dZ, int n, int H, float *__restrict__ db) {
-    const int h = blockIdx.x * blockDim.x + threadIdx.x;
-    if (h >= H) return;
-    float s = 0.0f;
-    for (int m = 0; m < n; ++m) s += dZ[(size_t)m * H + h];
-    db[h] = s;
-}
+__device__ __forceinline__ float to_f(float v) { return v; }
+__device__ __forceinline__ float to_f(uint16_t v) { return bf2f(v); }
 
-// Adam (bias-corrected) on the FP32 master parameters; refresh the BF16 copy
-// of the weight matrices.
+// out[h] = sum over rows m of (wt ? wt[m] : 1) * A[m][h] in a fixed order:
+// the 16 wavefronts of a block take rows w, w + 16, ... for 64 columns (one
+// per lane) and their partial sums are added in wavefront order.
+template <typename TA>
+__global__ __launch_bounds__(1024) void k_colsum(const TA *__restrict__ A, const float *__restrict__ wt, int n, int H,
+                                                 float *__restrict__ out) {
+    __shared__ float part[16][64];
+    const int lane = threadIdx.x & 63, w = (int)(threadIdx.x >> 6);
+    const int h = blockIdx.x * 64 + lane;
+    float s = 0.0f;
+    if (h < H) {
+        for (int m = w; m < n; m += 16) {
+            const float a = to_f(A[(size_t)m * H + h]);
+            s = wt ? fmaf(wt[m], a, s) : s + a;
+        }
+    }
+    part[w][lane] = s;
+    __syncthreads();
+    if (w == 0 && h < H) {
+        float t = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) t += part[k][lane];
+        out[h] = t;
+    }
+}
 __global__ void k_adam(float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m1,
                        float *__restrict__ m2, int64_t P, float lr, float b1, float b2, float eps, float c1, float c2) {
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < P; k += (int64_t)gridDim.x * blockDim.x) {
@@ -250,7 +271,7 @@ __global__ void k_to_bf16(const float *__restrict__ src, uint16_t *__restrict__ 
 }
 
 void launch_gemm(const Gemm &g, hipStream_t st) {
-    const int tiles = ((g.M + 31) / 32) * ((g.N + 31) / 32);
+    const int tiles = ((g.M + 15) / 16) * ((g.N + 15) / 16);
     k_gemm<<<(tiles + 3) / 4, 256, 0, st>>>(g);
 }
 
@@ -279,8 +300,8 @@ void forward(int D, int H, const float *params, const uint16_t *wb, const float 
                          (uint16_t *)(ws + w.H2)), st);
     launch_gemm(fwd_gemm((uint16_t *)(ws + w.H2), H, wb + o.bW3, n, H, H, params + o.b3, (float *)(ws + w.Z3),
                          (uint16_t *)(ws + w.H3)), st);
-    k_head_fwd<<<(n + 255) / 256, 256, 0, st>>>((uint16_t *)(ws + w.H3), params + o.w4, params + o.b4, n, H,
-                                                (float *)(ws + w.y));
+    k_head_fwd<<<(n + 3) / 4, 256, 0, st>>>((uint16_t *)(ws + w.H3), params + o.w4, params + o.b4, n, H,
+                                            (float *)(ws + w.y));
 }
 
 // Backward pass (after forward) into the gradient buffer of the workspace.
@@ -290,9 +311,11 @@ void backward(int D, int H, const float *params, const uint16_t *wb, const float
     const MlpWs w = mlp_ws(D, H, n);
     float *gr = (float *)(ws + w.grads);
     k_loss<<<1, 256, 0, st>>>((float *)(ws + w.y), fit, idx, mu, sigma, n, (float *)(ws + w.dy), (float *)(ws + w.loss));
-    k_head_bwd<<<(H + 255) / 256, 256, 0, st>>>((float *)(ws + w.dy), (uint16_t *)(ws + w.H3), (float *)(ws + w.Z3),
-                                                params + o.w4, n, H, gr + o.w4, gr + o.b4, (float *)(ws + w.dZ3),
-                                                (uint16_t *)(ws + w.dZ3b));
+    const int eblocks = (int)std::min<int64_t>(1024, ((int64_t)n * H + 255) / 256);
+    k_head_dz<<<eblocks, 256, 0, st>>>((float *)(ws + w.dy), (float *)(ws + w.Z3), params + o.w4, n, H,
+                                       (float *)(ws + w.dZ3), (uint16_t *)(ws + w.dZ3b));
+    k_colsum<uint16_t><<<(H + 63) / 64, 1024, 0, st>>>((uint16_t *)(ws + w.H3), (float *)(ws + w.dy), n, H, gr + o.w4);
+    k_colsum<float><<<1, 1024, 0, st>>>((float *)(ws + w.dy), nullptr, n, 1, gr + o.b4);
     const uint16_t *Hin[3] = {(uint16_t *)(ws + w.Xb), (uint16_t *)(ws + w.H1), (uint16_t *)(ws + w.H2)};
     const int Kin[3] = {D, H, H};
     const size_t gW[3] = {o.W1, o.W2, o.W3}, gB[3] = {o.b1, o.b2, o.b3}, bW[3] = {o.bW1, o.bW2, o.bW3};
@@ -306,7 +329,7 @@ void backward(int D, int H, const float *params, const uint16_t *wb, const float
         g.sam = 1; g.sak = H; g.sbk = Kin[l]; g.sbn = 1;
         g.epi = EPI_STORE; g.outf = gr + gW[l];
         launch_gemm(g, st);
-        k_colsum<<<(H + 255) / 256, 256, 0, st>>>(dZf[l], n, H, gr + gB[l]);
+        k_colsum<float><<<(H + 63) / 64, 1024, 0, st>>>(dZf[l], nullptr, n, H, gr + gB[l]);
         if (l > 0) {
             // dZ_{l-1}[m][k] = (sum_j dZ_l[m][j] W_l[j][k]) GELU'(Z_{l-1}[m][k])
             Gemm b = {};

@@ -94,3 +94,14 @@ def evals_to_reach(history, target):
         if r["best"] <= target:
             return r["evaluations"], r["wall_s"]
     return math.inf, math.inf
+
+
+def mean_history(histories):
+    """Seed average of equally long search histories: per iteration, the mean
+    best misfit so far, FD evaluations and wall seconds (runs of one mode use
+    the same FD evaluations per iteration, so the averages line up)."""
+    n = min(len(h) for h in histories)
+    return [{"iteration": k + 1,
+             "best": float(np.mean([h[k]["best"] for h in histories])),
+             "evaluations": float(np.mean([h[k]["evaluations"] for h in histories])),
+             "wall_s": float(np.mean([h[k]["wall_s"] for h in histories]))} for k in range(n)]

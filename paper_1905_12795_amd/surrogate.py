@@ -142,12 +142,16 @@ class Surrogate:
     def train(self, steps=None):
         """Adam steps on random mini-batches of the dataset; returns the last loss."""
         steps = self.steps_per_update if steps is None else steps
+        if steps <= 0 or self.count == 0:
+            return None
+        # every step's mini-batch indices in one upload: a host-to-device copy
+        # per step would wait for the previous step's kernels each time
+        b = min(self.batch, self.count)
+        idx = torch.as_tensor(self.rng.integers(0, self.count, (steps, b)).astype(np.int32), device=self.X.device)
         loss = None
-        for _ in range(steps):
-            b = min(self.batch, self.count)
-            idx = torch.as_tensor(self.rng.integers(0, self.count, b).astype(np.int32), device=self.X.device)
-            loss = self.net.train_step(self.X, self.f, idx, self.mu, self.sigma, self.lr)
-        return None if loss is None else float(loss.item())
+        for k in range(steps):
+            loss = self.net.train_step(self.X, self.f, idx[k], self.mu, self.sigma, self.lr)
+        return float(loss.item())
 
     def predict(self, X):
         """Host [n][D] -> host predicted standardised log-misfit [n]."""
