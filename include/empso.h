@@ -141,7 +141,8 @@ int empso_problem_get_info(const empso_problem *prob, empso_problem_info *info);
 int empso_vp_from_nodes(const empso_problem *prob, int32_t nmodels, const float *nodes_d,
                         float *vp_d, empso_stream stream);
 
-/* Workspace bytes for empso_forward_shots with nsh shots. */
+/* Workspace bytes for empso_forward_shots with nsh shots (0 for nsh = 0 and
+ * on invalid arguments). */
 size_t empso_forward_workspace_bytes(const empso_problem *prob, int32_t nsh);
 
 /* Model shots shot0 .. shot0+nsh-1 in the physical-grid model vp_d[nz][nx]
@@ -149,7 +150,10 @@ size_t empso_forward_workspace_bytes(const empso_problem *prob, int32_t nsh);
  * waits for the stream) and write traces_d[nsh][nt][nrec] (device, FP32).
  * The model is extended into the absorbing layer by nearest-value copy.
  * ERANGE if a velocity lies outside [vmin, vmax]. tuning may be NULL (library
- * default; the graph flag is ignored). The traces do not depend on the tuning. */
+ * default; the graph flag is ignored). The traces do not depend on the tuning.
+ * nsh = 0 (with 0 <= shot0 <= nshots) is an empty range: EMPSO_OK, nothing is
+ * enqueued and the pointer arguments are not used. EINVAL for nsh < 0 or a
+ * range outside the problem's shots. */
 int empso_forward_shots(const empso_problem *prob, const float *vp_d, int32_t shot0, int32_t nsh,
                         float *traces_d, void *ws, size_t ws_bytes, const empso_tuning *tuning,
                         empso_stream stream);
@@ -163,7 +167,8 @@ int empso_misfit(const float *a_d, const float *b_d, int64_t n, float *out_d,
                  void *ws, size_t ws_bytes, empso_stream stream);
 
 /* Workspace bytes for empso_fitness_batch over np particles; particle p uses
- * problem probs[prob_of_particle[p]] (host array). */
+ * problem probs[prob_of_particle[p]] (host array). 0 for an empty batch
+ * (np = 0) and on invalid arguments. */
 size_t empso_fitness_workspace_bytes(const empso_problem *const *probs, int32_t nprob,
                                      const int32_t *prob_of_particle, int32_t np);
 
@@ -178,7 +183,9 @@ size_t empso_fitness_workspace_bytes(const empso_problem *const *probs, int32_t 
  *                             ERANGE if outside [vmin, vmax] or not finite
  *   fitness_d[np]             device FP32 output; +inf if the wavefield of
  *                             some shot became non-finite
- * tuning may be NULL (library default). */
+ * tuning may be NULL (library default). np = 0 is an empty batch: EMPSO_OK,
+ * nothing is enqueued and the other arguments are not used; np < 0 is
+ * EINVAL. */
 int empso_fitness_batch(const empso_problem *const *probs, int32_t nprob,
                         const float *const *obs_d, const int32_t *prob_of_particle, int32_t np,
                         const double *nodes_h, int32_t ld_nodes, float *fitness_d,

@@ -1075,8 +1075,10 @@ extern "C" int empso_forward_shots(const empso_problem *p, const float *vp_d, in
                                    float *traces_d, void *ws, size_t ws_bytes, const empso_tuning *tuning,
                                    empso_stream stream) {
     clear_error();
-    if (!p || !vp_d || !traces_d || !ws) EMPSO_FAIL(EMPSO_EINVAL, "NULL argument");
-    if (nsh < 1 || shot0 < 0 || shot0 + nsh > p->g.nshots) EMPSO_FAIL(EMPSO_EINVAL, "shot range out of bounds");
+    if (!p) EMPSO_FAIL(EMPSO_EINVAL, "NULL argument");
+    if (nsh < 0 || shot0 < 0 || shot0 + nsh > p->g.nshots) EMPSO_FAIL(EMPSO_EINVAL, "shot range out of bounds");
+    if (nsh == 0) return EMPSO_OK;              // empty shot range: nothing to model or enqueue
+    if (!vp_d || !traces_d || !ws) EMPSO_FAIL(EMPSO_EINVAL, "NULL argument");
     if (reinterpret_cast<uintptr_t>(ws) % 256) EMPSO_FAIL(EMPSO_EINVAL, "workspace must be 256-byte aligned");
     if (ws_bytes < empso_forward_workspace_bytes(p, nsh)) EMPSO_FAIL(EMPSO_EWORKSPACE, "workspace too small");
     hipStream_t st = (hipStream_t)stream;
@@ -1142,8 +1144,9 @@ extern "C" int empso_fitness_batch(const empso_problem *const *probs, int32_t np
                                    float *fitness_d, void *ws, size_t ws_bytes, const empso_tuning *tuning,
                                    empso_stream stream) {
     clear_error();
+    if (np == 0) return EMPSO_OK;               // empty batch: nothing to evaluate or enqueue
     if (!probs || !obs_d || !pop || !nodes_h || !fitness_d || !ws) EMPSO_FAIL(EMPSO_EINVAL, "NULL argument");
-    if (nprob < 1 || np < 1) EMPSO_FAIL(EMPSO_EINVAL, "nprob and np must be >= 1");
+    if (nprob < 1 || np < 1) EMPSO_FAIL(EMPSO_EINVAL, "nprob >= 1 and np >= 0 required");
     if (reinterpret_cast<uintptr_t>(ws) % 256) EMPSO_FAIL(EMPSO_EINVAL, "workspace must be 256-byte aligned");
     for (int q = 0; q < nprob; ++q) {
         if (!probs[q]) EMPSO_FAIL(EMPSO_EINVAL, "probs[%d] is NULL", q);

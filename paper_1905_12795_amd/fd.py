@@ -177,7 +177,7 @@ class FitnessBatch:
         self._oh = (ctypes.c_void_p * len(self.obs))(*[o.data_ptr() for o in self.obs])
         self.Dmax = max(p.D for p in self.probs)
         need = lib.empso_fitness_workspace_bytes(self._ph, len(self.probs), self._pop_ptr(), self.np)
-        if need == 0:
+        if need == 0 and self.np > 0:
             raise ValueError("invalid batch")
         self.ws = workspace(need, device)
         self.out = torch.empty(self.np, dtype=torch.float32, device=device)
@@ -220,6 +220,8 @@ class FitnessBatch:
     def __call__(self, nodes, tuning=None):
         """nodes: host float64 [np][D] (row stride Dmax). Returns the device fitness tensor."""
         x = np.ascontiguousarray(np.asarray(nodes, dtype=np.float64))
+        if x.size == 0:
+            x = x.reshape(0, self.Dmax)
         if x.shape != (self.np, self.Dmax):
             raise ValueError("nodes must be [%d][%d]" % (self.np, self.Dmax))
         t = tuning if tuning is not None else self.tuning

@@ -246,3 +246,82 @@ def test_autotuner_picks_a_valid_tuning_with_identical_results(gfd):
     assert us > 0
     assert fb.time_tuning(X, fb.tuning, reps=2) > 0
     assert torch.equal(fb(X), ref)
+
+
+def test_empty_batch_and_empty_shot_range(gfd):
+    from paper_1905_12795_amd._lib import EmpsoError
+    g = config("tiny")
+    op, gp = _pair(gfd, g)
+    d = torch.zeros((1, gp.nt, gp.nrec), device="cuda")
+    out = gfd.FitnessBatch([gp], [d], [])(np.zeros((0, 6)))
+    assert tuple(out.shape) == (0,)
+    vp = torch.full((g["nz"], g["nx"]), 2000.0, device="cuda")
+    assert tuple(gfd.forward_shots(gp, vp, shot0=1, nsh=0).shape) == (0, gp.nt, gp.nrec)
+    with pytest.raises(EmpsoError) as ei:
+        gfd.forward_shots(gp, vp, shot0=0, nsh=2)              # the problem has one shot
+    assert ei.value.status == -1
+
+
+def _aniso_geom():
+    """dz != dx (the non-isotropic kernel variant), several x tiles, two shots."""
+    g = _small_geom()
+    g.update(dz=8.0, dx=12.0, nz=61, nx=251, tmax=0.3)
+    g["src"] = [[0.0, 1200.0], [16.0, 2400.0]]
+    g["rec"] = [[0.0, 12.0 * j] for j in range(0, 251, 2)]
+    return g
+
+
+def test_anisotropic_grid_matches_oracle_and_is_tiling_invariant(gfd):
+    g = _aniso_geom()
+    op, gp = _pair(gfd, g)
+    rng = np.random.default_rng(12)
+    truth = rng.uniform(1500, 2600, 12)
+    vp = ofd.vp_from_nodes(truth, 3, 4, g["nz"], g["nx"])
+    to = ofd.forward_shots(op, vp)
+    tg = gfd.forward_shots(gp, torch.tensor(vp, dtype=torch.float32, device="cuda")).cpu().numpy()
+    for s in range(2):
+        e = _rel(tg[s], to[s])
+        _say("anisotropic shot", s, "rel L2", e)
+        assert e <= REL, s
+    dobs = to.astype(np.float32)
+    X = rng.uniform(1400, 2700, (4, 12))
+    X[0] = truth
+    fo, _ = ofd.fitness_batch(op, X.astype(np.float32).astype(np.float64), dobs)
+    fb = gfd.FitnessBatch([gp], [torch.tensor(dobs, device="cuda")], [0] * 4)
+    n2 = float(np.sum(dobs.astype(np.float64) ** 2))
+    ref = None
+    for bz, T in ((20, 1), (40, 2), (80, 3), (160, 4)):
+        tu = gfd.default_tuning()
+        tu.bz, tu.tsteps = bz, T
+        got = fb(X, tuning=tu).clone()
+        ref = got if ref is None else ref
+        assert torch.equal(got, ref), (bz, T)
+    fg = ref.cpu().numpy().astype(np.float64)
+    for k in range(4):
+        assert _fit_close(fg[k], fo[k], n2), (k, fg[k], fo[k])
+
+
+def test_degenerate_geometry_matches_oracle(gfd):
+    """No absorbing layer (nbl = 0), a source on the corner grid point, a
+    single receiver, a 2 x 2 node grid."""
+    g = copy.deepcopy(config("tiny"))
+    g.update(nz=41, nx=61, nbl=0, tmax=0.25, ncz=2, ncx=2)
+    g["src"] = [[0.0, 0.0]]
+    g["rec"] = [[0.0, 300.0]]
+    g["node_lo"] = np.full(4, 1400.0)
+    g["node_hi"] = np.full(4, 2700.0)
+    op, gp = _pair(gfd, g)
+    vp = ofd.vp_from_nodes(np.array([1600.0, 1900.0, 2200.0, 2500.0]), 2, 2, g["nz"], g["nx"])
+    to = ofd.forward_shots(op, vp)
+    tg = gfd.forward_shots(gp, torch.tensor(vp, dtype=torch.float32, device="cuda")).cpu().numpy()
+    e = _rel(tg, to)
+    _say("degenerate geometry rel L2", e)
+    assert e <= REL
+    rng = np.random.default_rng(13)
+    X = rng.uniform(1400, 2700, (3, 4))
+    dobs = to.astype(np.float32)
+    fo, _ = ofd.fitness_batch(op, X.astype(np.float32).astype(np.float64), dobs)
+    fg = gfd.FitnessBatch([gp], [torch.tensor(dobs, device="cuda")], [0] * 3)(X).cpu().numpy()
+    n2 = float(np.sum(dobs.astype(np.float64) ** 2))
+    for k in range(3):
+        assert _fit_close(float(fg[k]), fo[k], n2), (k, fg[k], fo[k])

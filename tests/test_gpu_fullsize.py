@@ -109,3 +109,31 @@ def test_batched_three_sizes_full_size(gfd):
     _say("oracle fitness particle 0 %.1fs" % (time.time() - t0), fo, float(mixed[0]))
     n2 = float(np.sum(dobs[0].cpu().numpy().astype(np.float64) ** 2))
     assert _fit_close(float(mixed[0]), fo[0], n2)
+
+
+@pytest.mark.timeout(900)
+def test_full_workload_grid_sampled(gfd):
+    """The largest grid (601 x 1841 at 5 m + 40-point layer, nt = 21,636):
+    the first and last shots of the full workload through both entry points."""
+    g = copy.deepcopy(config("full"))
+    g["src"] = [g["src"][0], g["src"][-1]]
+    op = ofd.Problem(g)
+    gp = gfd.Problem(g, dt=op.dt, nt=op.nt)
+    vp = true_model(g)
+    t0 = time.time()
+    dobs = ofd.forward_shots(op, vp).astype(np.float32)
+    _say("oracle d_obs of 2 shots at full size %.1fs" % (time.time() - t0))
+    tg = gfd.forward_shots(gp, torch.tensor(vp, dtype=torch.float32, device="cuda")).cpu().numpy()
+    for s in range(2):
+        e = float(np.linalg.norm(tg[s] - dobs[s]) / np.linalg.norm(dobs[s]))
+        _say("full-size shot", s, "trace rel L2", e)
+        assert e <= REL
+    X = uniform_particles(2, g["node_lo"], g["node_hi"], g["particle_seed"])
+    fb = gfd.FitnessBatch([gp], [torch.tensor(dobs, device="cuda")], [0, 0])
+    fg = fb(X).cpu().numpy().astype(np.float64)
+    t0 = time.time()
+    fo, _ = ofd.fitness_batch(op, X.astype(np.float32).astype(np.float64), dobs)
+    _say("oracle fitness of 2 particles x 2 shots %.1fs" % (time.time() - t0), fo, fg)
+    n2 = float(np.sum(dobs.astype(np.float64) ** 2))
+    for k in range(2):
+        assert _fit_close(fg[k], fo[k], n2), (k, fg[k], fo[k])

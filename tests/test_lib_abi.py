@@ -99,3 +99,11 @@ def test_null_arguments(L):
     t = L.Tuning()
     assert L.lib.empso_default_tuning(ctypes.byref(t)) == 0
     assert t.tsteps >= 1 and t.bz > 0
+
+
+def test_empty_batch_is_a_no_op(L):
+    # np = 0: nothing to evaluate, nothing enqueued and no device call made
+    assert L.lib.empso_fitness_batch(None, 0, None, None, 0, None, 0, None, None, 0, None, None) == 0
+    assert L.lib.empso_fitness_batch(None, 1, None, None, -1, None, 1, None, None, 0, None, None) == -1
+    assert L.lib.empso_fitness_workspace_bytes(None, 1, None, 0) == 0
+    assert L.lib.empso_forward_shots(None, None, 0, 0, None, None, 0, None, None) == -1      # no problem
