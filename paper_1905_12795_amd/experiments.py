@@ -83,19 +83,34 @@ def surrogate(workload, iters, seeds, K, log):
         g["particles"] = config("surrogate")["particles"]      # 64 particles x K = 16 -> 1024 candidates
     prob = fd.Problem(g)
     dobs = search.observed_data(prob, true_model(g))
+    hist = {m: [] for m in ("plain", "screened", "random")}
     for seed in seeds:
         res = {"workload": workload, "seed": seed, "particles": g["particles"], "K": K, "iterations": iters}
         hp = search.run(g, dobs, prob, iters, "plain", seed=seed, log_path=log)
+        hist["plain"].append(hp)
         target = 1.01 * hp[-1]["best"]
         res.update(plain_final=hp[-1]["best"], plain_evals=hp[-1]["evaluations"], plain_wall=hp[-1]["wall_s"])
         for mode in ("screened", "random"):
             h = search.run(g, dobs, prob, iters, mode, seed=seed, K=K, log_path=log)
+            hist[mode].append(h)
             e, t = search.evals_to_reach(h, target)
             res.update({mode + "_final": h[-1]["best"], mode + "_evals_to_plain": e, mode + "_wall_to_plain": t})
             if mode == "screened":
                 rh = [r["surrogate_rho"] for r in h if "surrogate_rho" in r]
                 res["screened_mean_rho"] = float(np.mean(rh)) if rh else None
         _emit(res)
+    # seed-averaged best-misfit curves: a single search is chaotic
+    mean = {m: search.mean_history(h) for m, h in hist.items()}
+    target = 1.01 * mean["plain"][-1]["best"]
+    summ = {"workload": workload, "seeds": list(seeds), "summary": "seed-averaged best-misfit curves",
+            "plain_final": mean["plain"][-1]["best"], "plain_evals": mean["plain"][-1]["evaluations"],
+            "plain_wall": mean["plain"][-1]["wall_s"]}
+    for mode in ("screened", "random"):
+        e, t = search.evals_to_reach(mean[mode], target)
+        summ.update({mode + "_final": mean[mode][-1]["best"], mode + "_evals_to_plain": e,
+                     mode + "_wall_to_plain": t})
+    summ["curves"] = {m: [round(r["best"], 4) for r in mean[m]] for m in mean}
+    _emit(summ)
 
 
 def main():
