@@ -89,8 +89,26 @@ typedef struct {
     int32_t nrec;            /* receivers per shot (same spread for every shot)         */
     const double *rec_zx;    /* [nrec][2] receiver (z, x) positions                     */
     int32_t ncz, ncx;        /* regular control-node grid, corners included, >= 2 each  */
+                             /* (layered grid: ncz = number of levels, ncx ignored)     */
     double vmin, vmax;       /* hard velocity bounds; dt is checked against vmax        */
     double damp_R;           /* target reflection coefficient of the layer (e.g. 1e-3)  */
+    /* Optional layered node grid, the reading of the paper's irregular grid
+     * (Testing approach section: nodes built from a 1-D prior with a water
+     * layer on top). node_z == NULL selects the regular ncz x ncx grid.
+     * Otherwise there are ncz >= 2 depth levels at depths node_z[ncz]
+     * (metres, strictly increasing); level a holds level_nodes[a] >= 2 nodes
+     * at x positions node_x (metres, strictly increasing within a level,
+     * levels concatenated in order); the node vector of a particle lists the
+     * nodes in the same order, D = sum(level_nodes). Interpolation: linear
+     * along each level in x (constant beyond its first and last node), then
+     * linear in z between the two levels around the point (constant above
+     * the first and below the last level). A regular grid is the layered
+     * grid whose levels all hold the same ncx evenly spaced nodes.         */
+    const double *node_z;
+    const int32_t *level_nodes;
+    const double *node_x;
+    int32_t water_rows;      /* physical rows 0 .. water_rows-1 hold v_water (either grid) */
+    double v_water;          /* within [vmin, vmax] when water_rows > 0                  */
 } empso_geometry;
 
 /* Read-only facts about a problem (for sizing caller-owned arrays). */
@@ -99,6 +117,7 @@ typedef struct {
     int32_t Nz, Nx;          /* padded grid: nz + 2 nbl, nx + 2 nbl                    */
     int32_t row_stride;      /* floats per stored row of an internal field              */
     int64_t updates_per_run; /* Nz * Nx * (nt - 1): point updates of one shot           */
+    int32_t D;               /* node values per particle (ncz * ncx, or sum(level_nodes)) */
 } empso_problem_info;
 
 /* Tuning of the finite-difference kernels. Every valid tuning gives
@@ -134,10 +153,11 @@ void empso_problem_destroy(empso_problem *prob);
 
 int empso_problem_get_info(const empso_problem *prob, empso_problem_info *info);
 
-/* Bilinear two-grid interpolation (Testing approach section): control-node
- * velocities nodes_d[nmodels][ncz*ncx] (device, FP32, row-major z-major)
- * become vp_d[nmodels][nz][nx] (device, FP32). Node (a, b) sits at grid point
- * (a (nz-1)/(ncz-1), b (nx-1)/(ncx-1)). */
+/* Two-grid interpolation (Testing approach section): control-node velocities
+ * nodes_d[nmodels][D] (device, FP32) become vp_d[nmodels][nz][nx] (device,
+ * FP32). Regular grid: nodes row-major z-major, node (a, b) at grid point
+ * (a (nz-1)/(ncz-1), b (nx-1)/(ncx-1)), bilinear in each cell. Layered grid:
+ * as described with empso_geometry. Rows above water_rows hold v_water. */
 int empso_vp_from_nodes(const empso_problem *prob, int32_t nmodels, const float *nodes_d,
                         float *vp_d, empso_stream stream);
 

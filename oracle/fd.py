@@ -22,6 +22,13 @@ Conventions the paper leaves open, and the reading taken here:
     leaves it unchanged).
   * control nodes form a regular ncz x ncx grid whose corners are the corners
     of the physical grid; the padded layer copies the nearest physical value.
+  * the paper's irregular node grid (Testing approach section: nodes built
+    from a 1-D prior by resolution criteria it does not state, a water layer
+    fixed by the prior) is read as a layered grid: depth levels, each with its
+    own node x positions; linear along each level in x, then linear in z
+    between the two levels around a point, constant beyond the first and last
+    node of a level and above / below the first / last level; the top
+    water_rows physical rows hold the water velocity.
 """
 import ctypes
 import math
@@ -190,6 +197,66 @@ def vp_from_nodes(nodes, ncz, ncx, nz, nx):
             + t * (1 - u) * g[A + 1, B] + t * u * g[A + 1, B + 1])
 
 
+def vp_from_levels(nodes, node_z, level_nodes, node_x, nz, nx, dz, dx, water_rows=0, v_water=1500.0):
+    """Two-grid interpolation from a layered node grid (the reading of the
+    paper's irregular grid stated in the module header).
+
+    node_z[L] level depths (m, increasing); level a holds level_nodes[a] nodes
+    at x positions node_x (m, increasing within a level, levels concatenated,
+    the same order as `nodes`). Point (i, j) at z = i dz, x = j dx:
+      v_a(x) = linear interpolation of level a's nodes at x (held constant
+               beyond its first and last node),
+      v(z, x) = (1 - t) v_a(x) + t v_{a+1}(x) for z_a <= z <= z_{a+1},
+               t = (z - z_a)/(z_{a+1} - z_a); v_0 above the first level and
+               v_{L-1} below the last one;
+    rows i < water_rows hold v_water. Plain loops over grid points.
+    Pinned by: bilinear functions sampled on a rectilinear layout are
+    reproduced exactly, node values at node sites, linear interpolation along
+    a level row and across levels at a column (np.interp), the water rows and
+    the convex-combination bound.
+    """
+    nodes = np.asarray(nodes, dtype=np.float64)
+    node_z = np.asarray(node_z, dtype=np.float64)
+    node_x = np.asarray(node_x, dtype=np.float64)
+    L = len(node_z)
+    starts = np.concatenate([[0], np.cumsum(level_nodes)]).astype(np.int64)
+    if nodes.size != starts[-1] or node_x.size != starts[-1]:
+        raise ValueError("nodes and node_x must hold sum(level_nodes) values")
+
+    def along(a, x):
+        xs = node_x[starts[a]:starts[a + 1]]
+        vs = nodes[starts[a]:starts[a + 1]]
+        if x <= xs[0]:
+            return vs[0]
+        if x >= xs[-1]:
+            return vs[-1]
+        b = 0
+        while xs[b + 1] < x:
+            b += 1
+        u = (x - xs[b]) / (xs[b + 1] - xs[b])
+        return (1.0 - u) * vs[b] + u * vs[b + 1]
+
+    out = np.empty((nz, nx), dtype=np.float64)
+    for i in range(nz):
+        z = i * dz
+        if i < water_rows:
+            out[i, :] = v_water
+            continue
+        if z <= node_z[0]:
+            a, t = 0, 0.0
+        elif z >= node_z[-1]:
+            a, t = L - 2, 1.0
+        else:
+            a = 0
+            while node_z[a + 1] < z:
+                a += 1
+            t = (z - node_z[a]) / (node_z[a + 1] - node_z[a])
+        for j in range(nx):
+            x = j * dx
+            out[i, j] = (1.0 - t) * along(a, x) + t * along(a + 1, x)
+    return out
+
+
 def pad_edge(vp, nbl):
     """Extend a physical-grid field into the absorbing layer by nearest-value copy."""
     return np.pad(np.asarray(vp, dtype=np.float64), nbl, mode="edge")
@@ -294,7 +361,14 @@ class Problem:
         self.f0 = float(geom["f0"])
         self.src = [tuple(p) for p in geom["src"]]
         self.rec = [tuple(p) for p in geom["rec"]]
-        self.ncz, self.ncx = int(geom["ncz"]), int(geom["ncx"])
+        self.ncz, self.ncx = int(geom.get("ncz", 0)), int(geom.get("ncx", 0))
+        self.levels = None
+        if geom.get("node_z") is not None:
+            self.levels = (np.asarray(geom["node_z"], dtype=np.float64),
+                           [int(n) for n in geom["level_nodes"]],
+                           np.asarray(geom["node_x"], dtype=np.float64))
+        self.water_rows = int(geom.get("water_rows", 0))
+        self.v_water = float(geom.get("v_water", 1500.0))
         self.R = float(geom.get("damp_R", 1e-3))
         self.damp = damping_profile(self.nz, self.nx, self.nbl, self.dz, self.dx, self.vmax, self.R)
         self.wavelet = ricker(self.f0, self.dt, self.nt)
@@ -306,6 +380,21 @@ class Problem:
     @property
     def nshots(self):
         return len(self.src)
+
+    @property
+    def D(self):
+        return int(sum(self.levels[1])) if self.levels else self.ncz * self.ncx
+
+    def model(self, nodes):
+        """Physical-grid model of one particle (regular or layered node grid)."""
+        if self.levels:
+            z, n, x = self.levels
+            return vp_from_levels(nodes, z, n, x, self.nz, self.nx, self.dz, self.dx,
+                                  self.water_rows, self.v_water)
+        vp = vp_from_nodes(nodes, self.ncz, self.ncx, self.nz, self.nx)
+        if self.water_rows:
+            vp[:self.water_rows, :] = self.v_water
+        return vp
 
     @property
     def nrec(self):
@@ -341,14 +430,13 @@ def misfit(a, b):
 
 def fitness_batch(prob, nodes, d_obs, shots=None, threads=None):
     """Fitness of each particle: sum over shots of the misfit (Results section:
-    a particle's fitness needs all 50 shots). nodes[P][ncz*ncx] FP64,
+    a particle's fitness needs all 50 shots). nodes[P][D] FP64 (D node values),
     d_obs[nshots][nt][nrec]. Non-finite fitness maps to +inf.
     Returns (fitness[P], per-run misfit[P][len(shots)]).
     """
     nodes = np.atleast_2d(np.asarray(nodes, dtype=np.float64))
     shots = list(range(prob.nshots)) if shots is None else list(shots)
-    vels = [pad_edge(vp_from_nodes(n, prob.ncz, prob.ncx, prob.nz, prob.nx), prob.nbl)
-            for n in nodes]
+    vels = [pad_edge(prob.model(n), prob.nbl) for n in nodes]
     jobs = [(p, k, s) for p in range(len(nodes)) for k, s in enumerate(shots)]
 
     def one(job):

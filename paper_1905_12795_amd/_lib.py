@@ -29,13 +29,16 @@ class Geometry(ctypes.Structure):
                 ("src_zx", ctypes.POINTER(ctypes.c_double)), ("nrec", ctypes.c_int32),
                 ("rec_zx", ctypes.POINTER(ctypes.c_double)),
                 ("ncz", ctypes.c_int32), ("ncx", ctypes.c_int32),
-                ("vmin", ctypes.c_double), ("vmax", ctypes.c_double), ("damp_R", ctypes.c_double)]
+                ("vmin", ctypes.c_double), ("vmax", ctypes.c_double), ("damp_R", ctypes.c_double),
+                ("node_z", ctypes.POINTER(ctypes.c_double)), ("level_nodes", ctypes.POINTER(ctypes.c_int32)),
+                ("node_x", ctypes.POINTER(ctypes.c_double)), ("water_rows", ctypes.c_int32),
+                ("v_water", ctypes.c_double)]
 
 
 class ProblemInfo(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in
                 ("nz", "nx", "nbl", "nt", "nshots", "nrec", "ncz", "ncx", "Nz", "Nx", "row_stride")] + \
-               [("updates_per_run", ctypes.c_int64)]
+               [("updates_per_run", ctypes.c_int64), ("D", ctypes.c_int32)]
 
 
 class Tuning(ctypes.Structure):

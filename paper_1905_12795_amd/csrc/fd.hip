@@ -78,7 +78,7 @@ using namespace empso;
 struct empso_problem {
     empso_geometry g;
     int Nz, Nx, S;             // padded sizes, stored row stride (floats)
-    int D;                     // ncz * ncx
+    int D;                     // node values per particle
     std::vector<int> srcI, srcJ;   // padded indices per shot
     int recI;                  // padded receiver row
     int zlo, zhi;              // stored rows [zlo, zhi) are undamped along z (a_z = 0)
@@ -88,6 +88,14 @@ struct empso_problem {
     float *d_ax = nullptr;     // [Nx]
     int *d_recmap = nullptr;   // [Nx] receiver index of a padded column or -1
     int *d_reccol = nullptr;   // [nrec]
+    // node-to-grid interpolation tables (regular and layered node grids):
+    // row i lies between levels rowa[i] and rowa[i] + 1 at weight rowt[i]
+    // (rowa[i] = -1: a water row); on level a, column j lies between nodes
+    // cidx[a][j] and cidx[a][j] + 1 (indices into the node vector) at weight cu[a][j]
+    int *d_rowa = nullptr;     // [nz]
+    float *d_rowt = nullptr;   // [nz]
+    int *d_cidx = nullptr;     // [levels][nx]
+    float *d_cu = nullptr;     // [levels][nx]
     float c0, cz[4], cx[4], wscale;
 };
 
@@ -136,6 +144,10 @@ static void free_problem(empso_problem *p) {
     if (p->d_ax) (void)hipFree(p->d_ax);
     if (p->d_recmap) (void)hipFree(p->d_recmap);
     if (p->d_reccol) (void)hipFree(p->d_reccol);
+    if (p->d_rowa) (void)hipFree(p->d_rowa);
+    if (p->d_rowt) (void)hipFree(p->d_rowt);
+    if (p->d_cidx) (void)hipFree(p->d_cidx);
+    if (p->d_cu) (void)hipFree(p->d_cu);
     delete p;
 }
 
@@ -147,14 +159,38 @@ extern "C" int empso_problem_create(const empso_geometry *gp, empso_problem **ou
     const empso_geometry &g = *gp;
     if (g.nz < 2 || g.nx < 2 || g.nbl < 0 || g.nt < 1 || g.nshots < 1 || g.nrec < 1)
         EMPSO_FAIL(EMPSO_EINVAL, "sizes must be positive (nz, nx >= 2, nbl >= 0, nt, nshots, nrec >= 1)");
-    if (g.ncz < 2 || g.ncx < 2) EMPSO_FAIL(EMPSO_EINVAL, "ncz and ncx must be >= 2");
-    if (g.ncz > g.nz || g.ncx > g.nx) EMPSO_FAIL(EMPSO_EINVAL, "more control nodes than grid points");
+    const bool layered = g.node_z != nullptr;
+    int64_t D64 = (int64_t)g.ncz * g.ncx;
+    if (!layered) {
+        if (g.ncz < 2 || g.ncx < 2) EMPSO_FAIL(EMPSO_EINVAL, "ncz and ncx must be >= 2");
+        if (g.ncz > g.nz || g.ncx > g.nx) EMPSO_FAIL(EMPSO_EINVAL, "more control nodes than grid points");
+    } else {
+        if (g.ncz < 2 || g.ncz > g.nz) EMPSO_FAIL(EMPSO_EINVAL, "a layered grid needs 2 .. nz levels");
+        if (!g.level_nodes || !g.node_x) EMPSO_FAIL(EMPSO_EINVAL, "level_nodes / node_x is NULL");
+        D64 = 0;
+        for (int a = 0; a < g.ncz; ++a) {
+            if (!std::isfinite(g.node_z[a]) || (a > 0 && !(g.node_z[a] > g.node_z[a - 1])))
+                EMPSO_FAIL(EMPSO_EINVAL, "level depths must be finite and strictly increasing");
+            if (g.level_nodes[a] < 2 || g.level_nodes[a] > g.nx)
+                EMPSO_FAIL(EMPSO_EINVAL, "level %d: 2 .. nx nodes required", a);
+            for (int b = 0; b < g.level_nodes[a]; ++b) {
+                const double x = g.node_x[D64 + b];
+                if (!std::isfinite(x) || (b > 0 && !(x > g.node_x[D64 + b - 1])))
+                    EMPSO_FAIL(EMPSO_EINVAL, "level %d: node x positions must be finite and strictly increasing", a);
+            }
+            D64 += g.level_nodes[a];
+        }
+    }
+    if (D64 > (1 << 20)) EMPSO_FAIL(EMPSO_ENOTSUP, "too many control nodes");
+    if (g.water_rows < 0 || g.water_rows >= g.nz) EMPSO_FAIL(EMPSO_EINVAL, "water_rows must lie in [0, nz)");
     if (!(g.dz > 0) || !(g.dx > 0) || !(g.dt > 0) || !(g.f0 > 0) || !std::isfinite(g.dz) ||
         !std::isfinite(g.dx) || !std::isfinite(g.dt) || !std::isfinite(g.f0))
         EMPSO_FAIL(EMPSO_EINVAL, "dz, dx, dt, f0 must be positive and finite");
     if (!(g.vmin > 0) || !(g.vmax >= g.vmin) || !std::isfinite(g.vmax))
         EMPSO_FAIL(EMPSO_EINVAL, "need 0 < vmin <= vmax < inf");
     if (!(g.damp_R > 0 && g.damp_R < 1)) EMPSO_FAIL(EMPSO_EINVAL, "damp_R must lie in (0, 1)");
+    if (g.water_rows > 0 && !(g.v_water >= g.vmin && g.v_water <= g.vmax))
+        EMPSO_FAIL(EMPSO_EINVAL, "v_water must lie in [vmin, vmax]");
     if (!g.src_zx || !g.rec_zx) EMPSO_FAIL(EMPSO_EINVAL, "src_zx / rec_zx is NULL");
     const int64_t Nz64 = (int64_t)g.nz + 2 * (int64_t)g.nbl, Nx64 = (int64_t)g.nx + 2 * (int64_t)g.nbl;
     if (Nz64 > (1 << 20) || Nx64 > (1 << 20) || (Nz64 + 8) * (Nx64 + 72) > (int64_t)1 << 31)
@@ -167,10 +203,13 @@ extern "C" int empso_problem_create(const empso_geometry *gp, empso_problem **ou
     p->g = g;
     p->g.src_zx = nullptr;
     p->g.rec_zx = nullptr;
+    p->g.node_z = nullptr;
+    p->g.level_nodes = nullptr;
+    p->g.node_x = nullptr;
     p->Nz = (int)Nz64;
     p->Nx = (int)Nx64;
     p->S = (int)align_up((size_t)p->Nx + 2 * kRing, 64);
-    p->D = g.ncz * g.ncx;
+    p->D = (int)D64;
     for (int s = 0; s < g.nshots; ++s) {
         int i, j;
         if (!on_grid(g.src_zx[2 * s], g.dz, g.nz, &i) || !on_grid(g.src_zx[2 * s + 1], g.dx, g.nx, &j)) {
@@ -240,7 +279,67 @@ extern "C" int empso_problem_create(const empso_geometry *gp, empso_problem **ou
     }
     p->wscale = (float)(1.0 / (g.dz * g.dx));
 
+    // node-to-grid tables, in grid-index units: level a at row position
+    // zeta[a], node b of level a at column position xi[a][b]; a regular grid
+    // puts its nodes at a (nz-1)/(ncz-1) and b (nx-1)/(ncx-1)
+    const int nlev = g.ncz;
+    std::vector<double> zeta(nlev);
+    std::vector<std::vector<double>> xi(nlev);
+    std::vector<int> first(nlev);
+    for (int a = 0, k = 0; a < nlev; ++a) {
+        const int nb = layered ? g.level_nodes[a] : g.ncx;
+        zeta[a] = layered ? g.node_z[a] / g.dz : (double)a * (g.nz - 1) / (g.ncz - 1);
+        first[a] = k;
+        for (int b = 0; b < nb; ++b)
+            xi[a].push_back(layered ? g.node_x[k + b] / g.dx : (double)b * (g.nx - 1) / (g.ncx - 1));
+        k += nb;
+    }
+    std::vector<int> rowa(g.nz), cidx((size_t)nlev * g.nx);
+    std::vector<float> rowt(g.nz), cu((size_t)nlev * g.nx);
+    for (int i = 0; i < g.nz; ++i) {
+        int a = 0;
+        double t = 0.0;
+        if (i < g.water_rows) {
+            a = -1;
+        } else if (i <= zeta[0]) {
+            a = 0; t = 0.0;
+        } else if (i >= zeta[nlev - 1]) {
+            a = nlev - 2; t = 1.0;
+        } else {
+            while (zeta[a + 1] < i) ++a;
+            t = (i - zeta[a]) / (zeta[a + 1] - zeta[a]);
+        }
+        rowa[i] = a;
+        rowt[i] = (float)t;
+    }
+    for (int a = 0; a < nlev; ++a) {
+        const std::vector<double> &x = xi[a];
+        const int nb = (int)x.size();
+        for (int j = 0; j < g.nx; ++j) {
+            int b = 0;
+            double u = 0.0;
+            if (j <= x[0]) {
+                b = 0; u = 0.0;
+            } else if (j >= x[nb - 1]) {
+                b = nb - 2; u = 1.0;
+            } else {
+                while (x[b + 1] < j) ++b;
+                u = (j - x[b]) / (x[b + 1] - x[b]);
+            }
+            cidx[(size_t)a * g.nx + j] = first[a] + b;
+            cu[(size_t)a * g.nx + j] = (float)u;
+        }
+    }
+
     hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = hipMalloc(&p->d_rowa, sizeof(int) * g.nz);
+    if (e == hipSuccess) e = hipMalloc(&p->d_rowt, sizeof(float) * g.nz);
+    if (e == hipSuccess) e = hipMalloc(&p->d_cidx, sizeof(int) * cidx.size());
+    if (e == hipSuccess) e = hipMalloc(&p->d_cu, sizeof(float) * cu.size());
+    if (e == hipSuccess) e = hipMemcpy(p->d_rowa, rowa.data(), sizeof(int) * g.nz, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p->d_rowt, rowt.data(), sizeof(float) * g.nz, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p->d_cidx, cidx.data(), sizeof(int) * cidx.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p->d_cu, cu.data(), sizeof(float) * cu.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMalloc(&p->d_wav, sizeof(float) * g.nt);
     if (e == hipSuccess) e = hipMalloc(&p->d_az, sizeof(float) * p->Nz);
     if (e == hipSuccess) e = hipMalloc(&p->d_ax, sizeof(float) * p->Nx);
@@ -276,6 +375,7 @@ extern "C" int empso_problem_get_info(const empso_problem *p, empso_problem_info
     info->Nx = p->Nx;
     info->row_stride = p->S;
     info->updates_per_run = (int64_t)p->Nz * p->Nx * (int64_t)(p->g.nt > 0 ? p->g.nt - 1 : 0);
+    info->D = p->D;
     return EMPSO_OK;
 }
 
@@ -306,11 +406,26 @@ struct RunDesc {
     float c0, cz1, cz2, cz3, cz4, cx1, cx2, cx3, cx4, wscale;
 };
 
+// Node-to-grid interpolation tables of a problem (see empso_problem).
+struct NodeMap {
+    const int *rowa;
+    const float *rowt;
+    const int *cidx;
+    const float *cu;
+    int nx;
+    float v_water;
+};
+
+static NodeMap node_map(const empso_problem *p) {
+    return NodeMap{p->d_rowa, p->d_rowt, p->d_cidx, p->d_cu, p->g.nx, (float)p->g.v_water};
+}
+
 struct CoefDesc {
     float *C;                   // output coefficient field
-    const float *nodes;         // [ncz*ncx] (node mode) or NULL
+    const float *nodes;         // [D] (node mode) or NULL
     const float *vp;            // [nz][nx] (model mode) or NULL
-    int nz, nx, nbl, ncz, ncx, Nz, Nx, S;
+    NodeMap map;
+    int nz, nx, nbl, Nz, Nx, S;
     float dt;
 };
 
@@ -318,29 +433,29 @@ struct CoefDesc {
 // Kernels
 // ---------------------------------------------------------------------------
 
-// Bilinear interpolation of a regular node grid at physical grid point (i, j).
-// Cell indices come from exact integer division so that node rows/columns that
-// fall on grid points are reproduced exactly.
-__device__ __forceinline__ float bilinear_at(const float *nd, int ncz, int ncx, int nz, int nx, int i, int j) {
-    int ni = i * (ncz - 1), a = ni / (nz - 1);
-    float t = (float)(ni - a * (nz - 1)) / (float)(nz - 1);
-    if (a >= ncz - 1) { a = ncz - 2; t = 1.0f; }
-    int nj = j * (ncx - 1), b = nj / (nx - 1);
-    float u = (float)(nj - b * (nx - 1)) / (float)(nx - 1);
-    if (b >= ncx - 1) { b = ncx - 2; u = 1.0f; }
-    const float v00 = nd[a * ncx + b], v01 = nd[a * ncx + b + 1];
-    const float v10 = nd[(a + 1) * ncx + b], v11 = nd[(a + 1) * ncx + b + 1];
-    return (1.0f - t) * (1.0f - u) * v00 + (1.0f - t) * u * v01 + t * (1.0f - u) * v10 + t * u * v11;
+// Two-grid interpolation at physical grid point (i, j): linear along the two
+// levels around row i, then linear between them (bilinear in each cell of a
+// regular grid); water rows hold the water velocity.
+__device__ __forceinline__ float node_interp(const float *nd, const NodeMap &m, int i, int j) {
+    const int a = m.rowa[i];
+    if (a < 0) return m.v_water;
+    const float t = m.rowt[i];
+    const size_t k0 = (size_t)a * m.nx + j, k1 = k0 + m.nx;
+    const int b0 = m.cidx[k0], b1 = m.cidx[k1];
+    const float u0 = m.cu[k0], u1 = m.cu[k1];
+    const float v0 = (1.0f - u0) * nd[b0] + u0 * nd[b0 + 1];
+    const float v1 = (1.0f - u1) * nd[b1] + u1 * nd[b1 + 1];
+    return (1.0f - t) * v0 + t * v1;
 }
 
-__global__ void k_vp_from_nodes(const float *__restrict__ nodes, float *__restrict__ vp, int ncz, int ncx,
+__global__ void k_vp_from_nodes(const float *__restrict__ nodes, float *__restrict__ vp, const NodeMap map, int D,
                                 int nz, int nx) {
     const int m = blockIdx.y;
-    const float *nd = nodes + (size_t)m * ncz * ncx;
+    const float *nd = nodes + (size_t)m * D;
     const int64_t npts = (int64_t)nz * nx;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < npts; k += (int64_t)gridDim.x * blockDim.x) {
         int i = (int)(k / nx), j = (int)(k - (int64_t)i * nx);
-        vp[(size_t)m * npts + k] = bilinear_at(nd, ncz, ncx, nz, nx, i, j);
+        vp[(size_t)m * npts + k] = node_interp(nd, map, i, j);
     }
 }
 
@@ -356,8 +471,7 @@ __global__ void k_coef(const CoefDesc *__restrict__ cds) {
         if (I >= 0 && I < cd.Nz && J >= 0 && J < cd.Nx) {
             const int i = min(max(I - cd.nbl, 0), cd.nz - 1);
             const int j = min(max(J - cd.nbl, 0), cd.nx - 1);
-            const float v = cd.nodes ? bilinear_at(cd.nodes, cd.ncz, cd.ncx, cd.nz, cd.nx, i, j)
-                                     : cd.vp[(size_t)i * cd.nx + j];
+            const float v = cd.nodes ? node_interp(cd.nodes, cd.map, i, j) : cd.vp[(size_t)i * cd.nx + j];
             const float vd = v * cd.dt;
             val = vd * vd;
         }
@@ -913,7 +1027,8 @@ static void build_header(Plan &pl, unsigned char *ws, const std::vector<const em
             for (int d = 0; d < p->D; ++d) nd[(size_t)k * Dmax + d] = (float)nodes_h[(size_t)k * ld_nodes + d];
             c.nodes = reinterpret_cast<const float *>(ws + L.nodes_off) + (size_t)k * Dmax;
         }
-        c.nz = p->g.nz; c.nx = p->g.nx; c.nbl = p->g.nbl; c.ncz = p->g.ncz; c.ncx = p->g.ncx;
+        c.nz = p->g.nz; c.nx = p->g.nx; c.nbl = p->g.nbl;
+        c.map = node_map(p);
         c.Nz = p->Nz; c.Nx = p->Nx; c.S = p->S;
         c.dt = (float)p->g.dt;
     }
@@ -1030,7 +1145,7 @@ extern "C" int empso_vp_from_nodes(const empso_problem *p, int32_t nmodels, cons
     if (nmodels < 1 || nmodels > 65535) EMPSO_FAIL(EMPSO_EINVAL, "nmodels must be in [1, 65535]");
     const int64_t npts = (int64_t)p->g.nz * p->g.nx;
     const int bx = (int)std::min<int64_t>(1024, (npts + 255) / 256);
-    k_vp_from_nodes<<<dim3(bx, nmodels), 256, 0, (hipStream_t)stream>>>(nodes_d, vp_d, p->g.ncz, p->g.ncx, p->g.nz,
+    k_vp_from_nodes<<<dim3(bx, nmodels), 256, 0, (hipStream_t)stream>>>(nodes_d, vp_d, node_map(p), p->D, p->g.nz,
                                                                          p->g.nx);
     EMPSO_HIP(hipGetLastError());
     return EMPSO_OK;

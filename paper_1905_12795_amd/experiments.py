@@ -78,7 +78,7 @@ def throughput(workload, particles, calls):
 
 def surrogate(workload, iters, seeds, K, log):
     g = config(workload)
-    if workload == "realistic":
+    if workload in ("realistic", "irregular"):
         g = dict(g)
         g["particles"] = config("surrogate")["particles"]      # 64 particles x K = 16 -> 1024 candidates
     prob = fd.Problem(g)
@@ -117,11 +117,11 @@ def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
     t = sub.add_parser("throughput")
-    t.add_argument("--workload", default="batched", choices=["tiny", "realistic", "batched", "full"])
+    t.add_argument("--workload", default="batched", choices=["tiny", "realistic", "batched", "full", "irregular"])
     t.add_argument("--particles", type=int, default=0)
     t.add_argument("--calls", type=int, default=3)
     s = sub.add_parser("surrogate")
-    s.add_argument("--workload", default="mini", choices=["mini", "realistic"])
+    s.add_argument("--workload", default="mini", choices=["mini", "realistic", "irregular"])
     s.add_argument("--iters", type=int, default=30)
     s.add_argument("--seeds", default="1,2,3")
     s.add_argument("--K", type=int, default=16)

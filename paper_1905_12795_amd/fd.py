@@ -69,8 +69,10 @@ class Problem:
         self._src = np.ascontiguousarray(np.asarray(geom["src"], dtype=np.float64).reshape(-1, 2))
         self._rec = np.ascontiguousarray(np.asarray(geom["rec"], dtype=np.float64).reshape(-1, 2))
         lo = np.asarray(geom["node_lo"], dtype=np.float64)
+        water_rows = int(geom.get("water_rows", 0))
+        v_water = float(geom.get("v_water", 1500.0))
         if vmin is None:
-            vmin = float(lo.min())
+            vmin = float(min(lo.min(), v_water)) if water_rows else float(lo.min())
         g = Geometry()
         g.nz, g.nx = int(geom["nz"]), int(geom["nx"])
         g.dz, g.dx = float(geom["dz"]), float(geom["dx"])
@@ -80,9 +82,18 @@ class Problem:
         g.src_zx = self._src.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         g.nrec = self._rec.shape[0]
         g.rec_zx = self._rec.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-        g.ncz, g.ncx = int(geom["ncz"]), int(geom["ncx"])
+        g.ncz, g.ncx = int(geom.get("ncz", 0)), int(geom.get("ncx", 0))
         g.vmin, g.vmax = float(vmin), float(geom["vmax"])
         g.damp_R = float(geom.get("damp_R", 1e-3))
+        if geom.get("node_z") is not None:          # layered node grid
+            self._nz_ = np.ascontiguousarray(np.asarray(geom["node_z"], dtype=np.float64))
+            self._nn_ = np.ascontiguousarray(np.asarray(geom["level_nodes"], dtype=np.int32))
+            self._nx_ = np.ascontiguousarray(np.asarray(geom["node_x"], dtype=np.float64))
+            g.ncz = int(self._nz_.size)
+            g.node_z = self._nz_.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            g.level_nodes = self._nn_.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+            g.node_x = self._nx_.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        g.water_rows, g.v_water = water_rows, v_water
         h = ctypes.c_void_p()
         check(lib.empso_problem_create(ctypes.byref(g), ctypes.byref(h)))
         self.handle = h
@@ -109,7 +120,7 @@ class Problem:
 
     @property
     def D(self):
-        return self.info.ncz * self.info.ncx
+        return int(self.info.D)
 
     @property
     def updates_per_run(self):
@@ -117,7 +128,7 @@ class Problem:
 
 
 def vp_from_nodes(prob, nodes, out=None):
-    """nodes[nm][ncz*ncx] FP32 (device) -> vp[nm][nz][nx] FP32 (device)."""
+    """nodes[nm][D] FP32 (device) -> vp[nm][nz][nx] FP32 (device) (two-grid interpolation)."""
     _need(nodes, torch.float32, name="nodes")
     nm = nodes.shape[0]
     if nodes.dim() != 2 or nodes.shape[1] != prob.D:

@@ -325,3 +325,49 @@ def test_degenerate_geometry_matches_oracle(gfd):
     n2 = float(np.sum(dobs.astype(np.float64) ** 2))
     for k in range(3):
         assert _fit_close(float(fg[k]), fo[k], n2), (k, fg[k], fo[k])
+
+
+def _layered_small_geom():
+    """A layered node grid with node x positions off the grid columns, a water
+    layer of 3 rows and several x tiles."""
+    g = _small_geom()
+    del g["ncz"], g["ncx"]
+    g["node_z"] = [30.0, 175.0, 420.0, 600.0]
+    g["level_nodes"] = [5, 4, 3, 2]
+    g["node_x"] = [0.0, 733.0, 1500.0, 2271.0, 3000.0, 115.0, 1000.0, 2000.0, 2950.0,
+                   0.0, 1333.3, 3000.0, 400.0, 2600.0]
+    g["water_rows"], g["v_water"] = 3, 1480.0
+    g["node_lo"], g["node_hi"] = np.full(14, 1400.0), np.full(14, 2700.0)
+    return g
+
+
+def test_layered_node_grid_with_water_matches_oracle(gfd):
+    g = _layered_small_geom()
+    op, gp = _pair(gfd, g)
+    assert gp.D == op.D == 14
+    rng = np.random.default_rng(14)
+    X = rng.uniform(1400, 2700, (5, 14))
+    vg = gfd.vp_from_nodes(gp, torch.tensor(X, dtype=torch.float32, device="cuda")).cpu().numpy()
+    for k in range(5):
+        vo = op.model(X[k].astype(np.float32).astype(np.float64))
+        assert np.max(np.abs(vg[k] - vo) / vo) < 2e-6, k
+        assert np.all(vg[k][:3] == np.float32(1480.0))
+    to = ofd.forward_shots(op, op.model(X[0]))
+    dobs = to.astype(np.float32)
+    fo, _ = ofd.fitness_batch(op, X.astype(np.float32).astype(np.float64), dobs)
+    fg = gfd.FitnessBatch([gp], [torch.tensor(dobs, device="cuda")], [0] * 5)(X).cpu().numpy()
+    n2 = float(np.sum(dobs.astype(np.float64) ** 2))
+    _say("layered fitness rel", np.abs(fg - fo) / np.maximum(fo, 1e-30))
+    for k in range(5):
+        assert _fit_close(float(fg[k]), fo[k], n2), (k, fg[k], fo[k])
+
+
+def test_irregular_workload_vp_matches_oracle(gfd):
+    g = config("irregular")
+    op, gp = _pair(gfd, g)
+    rng = np.random.default_rng(15)
+    X = g["node_lo"] + (g["node_hi"] - g["node_lo"]) * rng.random((2, gp.D))
+    vg = gfd.vp_from_nodes(gp, torch.tensor(X, dtype=torch.float32, device="cuda")).cpu().numpy()
+    for k in range(2):
+        vo = op.model(X[k].astype(np.float32).astype(np.float64))
+        assert np.max(np.abs(vg[k] - vo) / vo) < 2e-6, k

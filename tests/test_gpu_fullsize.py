@@ -137,3 +137,23 @@ def test_full_workload_grid_sampled(gfd):
     n2 = float(np.sum(dobs.astype(np.float64) ** 2))
     for k in range(2):
         assert _fit_close(fg[k], fo[k], n2), (k, fg[k], fo[k])
+
+
+@pytest.mark.timeout(600)
+def test_irregular_workload_full_size_sampled(gfd):
+    """The realistic acquisition with a layered node grid and a water layer:
+    the whole 32-particle batch on the GPU, two particles sampled by the oracle."""
+    g = config("irregular")
+    op = ofd.Problem(g)
+    gp = gfd.Problem(g, dt=op.dt, nt=op.nt)
+    t0 = time.time()
+    dobs = ofd.forward_shots(op, true_model(g)).astype(np.float32)
+    _say("oracle d_obs %.1fs" % (time.time() - t0))
+    X = uniform_particles(g["particles"], g["node_lo"], g["node_hi"], g["particle_seed"])
+    fg = gfd.FitnessBatch([gp], [torch.tensor(dobs, device="cuda")], [0] * len(X))(X).cpu().numpy()
+    sample = [3, 29]
+    fo, _ = ofd.fitness_batch(op, X[sample].astype(np.float32).astype(np.float64), dobs)
+    _say("irregular fitness", fo, fg[sample])
+    n2 = float(np.sum(dobs.astype(np.float64) ** 2))
+    for i, k in enumerate(sample):
+        assert _fit_close(float(fg[k]), fo[i], n2), (k, fg[k], fo[i])

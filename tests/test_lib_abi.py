@@ -63,6 +63,13 @@ def _geom(L, **kw):
             src = np.asarray(v, dtype=np.float64)
         elif k == "rec":
             rec = np.asarray(v, dtype=np.float64)
+        elif k == "levels":                               # (node_z, level_nodes, node_x)
+            z, n, x = (np.asarray(v[0], np.float64), np.asarray(v[1], np.int32), np.asarray(v[2], np.float64))
+            g._lv = (z, n, x)
+            g.ncz = len(z)
+            g.node_z = z.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            g.level_nodes = n.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+            g.node_x = x.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         else:
             setattr(g, k, v)
     g.nshots, g.nrec = len(src), len(rec)
@@ -82,6 +89,13 @@ def _geom(L, **kw):
     (dict(rec=[[0.0, 10.0], [10.0, 20.0]]), -6),          # receivers on two rows
     (dict(rec=[[0.0, 10.0], [0.0, 10.0]]), -6),           # two receivers on one point
     (dict(src=[[0.0, 2000.0]]), -6),                      # source outside the grid
+    (dict(levels=([100.0, 50.0], [2, 2], [0, 500, 0, 500])), -1),          # levels not increasing
+    (dict(levels=([0.0, 500.0], [2, 1], [0, 500, 0])), -1),                # a level with one node
+    (dict(levels=([0.0, 500.0], [2, 2], [0, 500, 500, 0])), -1),          # x not increasing in a level
+    (dict(levels=([0.0, 500.0], [2, 2], [0, np.nan, 0, 500])), -1),       # non-finite position
+    (dict(water_rows=101), -1),                                             # water_rows >= nz
+    (dict(water_rows=-1), -1),
+    (dict(water_rows=4, v_water=1000.0), -1),                               # water velocity below vmin
 ])
 def test_problem_create_rejects_on_host(L, kw, status):
     g = _geom(L, **kw)

@@ -124,3 +124,36 @@ def test_planted_weight_sign_error_is_caught(monkeypatch, k):
     monkeypatch.setattr(fd, "fd_weights", lambda M=4: bad)
     err = _green_error()
     assert not (err <= 1e-2), err          # large or non-finite
+
+
+LEVEL_MUTATIONS = {
+    "z weights swapped": ("out[i, j] = (1.0 - t) * along(a, x) + t * along(a + 1, x)",
+                          "out[i, j] = t * along(a, x) + (1.0 - t) * along(a + 1, x)"),
+    "x weights swapped": ("return (1.0 - u) * vs[b] + u * vs[b + 1]", "return u * vs[b] + (1.0 - u) * vs[b + 1]"),
+    "z measured from the wrong level": ("t = (z - node_z[a]) / (node_z[a + 1] - node_z[a])",
+                                        "t = (z - node_z[a + 1]) / (node_z[a + 1] - node_z[a])"),
+    "last level not clamped": ("a, t = L - 2, 1.0", "a, t = L - 2, 0.0"),
+    "water rows ignored": ("        if i < water_rows:\n", "        if i < 0:\n"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(LEVEL_MUTATIONS))
+def test_planted_level_interpolation_mistake_is_caught(monkeypatch, name):
+    import inspect
+    import textwrap
+
+    from tests import test_oracle_model as pins
+    old, new = LEVEL_MUTATIONS[name]
+    src = textwrap.dedent(inspect.getsource(fd.vp_from_levels))
+    assert old in src, name
+    ns = dict(fd.__dict__)
+    exec(compile(src.replace(old, new, 1), "<mutant>", "exec"), ns)
+    monkeypatch.setattr(fd, "vp_from_levels", ns["vp_from_levels"])
+    caught = 0
+    for pin in (pins.test_levels_reproduce_bilinear_functions_on_a_rectilinear_layout,
+                pins.test_levels_node_values_rows_columns_and_bounds, pins.test_levels_brute_force_point):
+        try:
+            pin()
+        except AssertionError:
+            caught += 1
+    assert caught > 0, name

@@ -9,7 +9,12 @@ Keys (all SI units: metres, seconds, m/s, Hz):
                    at velocity vmax (both sides compute that limit themselves).
   src, rec         [n][2] (z, x) positions of shots and receivers.
   ncz, ncx         regular control-node grid (corners included).
-  node_lo, node_hi [ncz*ncx] search box per node (row-major, z-major).
+  node_z, level_nodes, node_x
+                   optional layered node grid instead (depth levels with
+                   their own node x positions, metres; see layered_nodes).
+  water_rows, v_water
+                   optional water layer: the top physical rows are fixed.
+  node_lo, node_hi [D] search box per node (row-major z-major, or level by level).
   damp_R           target reflection coefficient of the absorbing layer.
   model            recipe of the true model (generator name and seed).
   particles, particle_seed   swarm size and seed of the initial draw.
@@ -20,7 +25,7 @@ import numpy as np
 
 from .models import two_layer, layered_faulted
 
-CONFIG_NAMES = ("tiny", "realistic", "batched", "surrogate", "full", "mini")
+CONFIG_NAMES = ("tiny", "realistic", "batched", "surrogate", "full", "mini", "irregular")
 
 
 def _prior_box(nz, dz, ncz, ncx, v0=1500.0, v1=5500.0, lo_min=1400.0, hi_max=6000.0):
@@ -34,6 +39,42 @@ def _prior_box(nz, dz, ncz, ncx, v0=1500.0, v1=5500.0, lo_min=1400.0, hi_max=600
     lo = np.maximum(lo_min, 0.7 * vprior)
     hi = np.minimum(hi_max, 1.3 * vprior)
     return np.repeat(lo, ncx), np.repeat(hi, ncx)
+
+
+def layered_nodes(nz, nx, dz, dx, water_rows, v0, v1, kz, kx):
+    """Node layout built from a 1-D prior v(z) rising linearly from v0 at the
+    water bottom to v1 at the grid bottom: the first level sits at the water
+    bottom, each next level kz * v(z) deeper (the last one at the bottom of
+    the grid), and level a holds evenly spaced nodes about kx * v(z_a) apart
+    across the grid (at least 2), so the grid coarsens where the prior is
+    faster. Returns (node_z, level_nodes, node_x, prior at each level)."""
+    zw, zmax, xmax = water_rows * dz, (nz - 1) * dz, (nx - 1) * dx
+    prior = lambda z: v0 + (v1 - v0) * (z - zw) / (zmax - zw)          # noqa: E731
+    node_z = [zw]
+    while node_z[-1] + kz * prior(node_z[-1]) < zmax - 0.5 * kz * prior(node_z[-1]):
+        node_z.append(node_z[-1] + kz * prior(node_z[-1]))
+    node_z.append(zmax)
+    counts, xs = [], []
+    for z in node_z:
+        n = max(2, int(round(xmax / (kx * prior(z)))) + 1)
+        counts.append(n)
+        xs.append(np.linspace(0.0, xmax, n))
+    return np.array(node_z), counts, np.concatenate(xs), np.array([prior(z) for z in node_z])
+
+
+def _level_box(node_z, counts, prior, first=(0.8, 1.2), last=(0.7, 1.3), lo_min=1400.0, hi_max=6000.0):
+    """Search box per node: the first and last levels span fractions of the
+    prior velocity there; the bounds of the levels in between lie on the
+    lines joining those of the first and last levels (linear in depth);
+    everything is clipped to [lo_min, hi_max] (hi_max is the velocity the
+    time step is chosen for)."""
+    z0, z1 = node_z[0], node_z[-1]
+    lo0, hi0 = first[0] * prior[0], first[1] * prior[0]
+    lo1, hi1 = last[0] * prior[-1], last[1] * prior[-1]
+    w = (node_z - z0) / (z1 - z0)
+    lo = np.maximum(lo_min, lo0 + (lo1 - lo0) * w)
+    hi = np.minimum(hi_max, hi0 + (hi1 - hi0) * w)
+    return np.repeat(lo, counts), np.repeat(hi, counts)
 
 
 def _surface_line(n, spacing):
@@ -90,6 +131,17 @@ def config(name):
         return out
     if name in ("full", 4):
         return _layered_geometry(601, 1841, 5, 32, 10, 6.0, 4.0, 8, 20, seed=8, pseed=9, npart=128)
+    if name == "irregular":
+        # the realistic acquisition with the paper's kind of parameterisation:
+        # a layered node grid from a 1-D prior (1500 -> 5500 m/s), a water
+        # layer of 4 rows at 1500 m/s, and depth-dependent search ranges
+        g = _layered_geometry(301, 921, 10, 16, 20, 5.0, 3.0, 5, 12, seed=3, pseed=4, npart=32)
+        del g["ncz"], g["ncx"]
+        g["water_rows"], g["v_water"] = 4, 1500.0
+        node_z, counts, node_x, prior = layered_nodes(301, 921, 10.0, 10.0, 4, 1500.0, 5500.0, 0.12, 0.6)
+        g["node_z"], g["level_nodes"], g["node_x"] = node_z, counts, node_x
+        g["node_lo"], g["node_hi"] = _level_box(node_z, counts, prior)
+        return g
     if name == "mini":
         # a reduced realistic search used to compare plain and screened swarms
         # quickly: 1 km x 3 km at 10 m, 4 shots, 151 receivers, 4 Hz, 1.5 s,
@@ -106,13 +158,18 @@ def config(name):
 
 
 def true_model(geom):
-    """Generate the seeded true velocity model vp[nz][nx] (float64) of a geometry."""
+    """Generate the seeded true velocity model vp[nz][nx] (float64) of a geometry
+    (with its water layer, if it has one)."""
     m = geom["model"]
     if m["kind"] == "two_layer":
         vp, _ = two_layer(geom["nz"], geom["nx"], geom["dz"], geom["dx"],
                           m["v_top"], m["v_bottom"], m["seed"])
-        return vp
-    if m["kind"] == "layered_faulted":
-        return layered_faulted(geom["nz"], geom["nx"], geom["dz"], geom["dx"], m["seed"],
-                               v_bottom=m.get("v_bottom", 5500.0))
-    raise KeyError(m["kind"])
+    elif m["kind"] == "layered_faulted":
+        vp = layered_faulted(geom["nz"], geom["nx"], geom["dz"], geom["dx"], m["seed"],
+                             v_bottom=m.get("v_bottom", 5500.0))
+    else:
+        raise KeyError(m["kind"])
+    w = int(geom.get("water_rows", 0))
+    if w:
+        vp[:w, :] = geom["v_water"]
+    return vp
