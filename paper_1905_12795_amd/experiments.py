@@ -53,7 +53,7 @@ def throughput(workload, particles, calls):
         lo, hi = g["node_lo"], g["node_hi"]
         seed = g["particle_seed"]
     t0 = time.perf_counter()
-    obs = [search.observed_data(p, true_model(g)) for p, g in zip(probs, geoms)]
+    obs = [search.observed_for(g, p, true_model(g)) for p, g in zip(probs, geoms)]
     torch.cuda.synchronize()
     _emit({"stage": "observed data", "seconds": time.perf_counter() - t0})
     X = uniform_particles(npart, lo, hi, seed)
@@ -78,11 +78,11 @@ def throughput(workload, particles, calls):
 
 def surrogate(workload, iters, seeds, K, log):
     g = config(workload)
-    if workload in ("realistic", "irregular"):
+    if workload in ("realistic", "irregular", "crime_free"):
         g = dict(g)
         g["particles"] = config("surrogate")["particles"]      # 64 particles x K = 16 -> 1024 candidates
     prob = fd.Problem(g)
-    dobs = search.observed_data(prob, true_model(g))
+    dobs = search.observed_for(g, prob, true_model(g))
     hist = {m: [] for m in ("plain", "screened", "random")}
     for seed in seeds:
         res = {"workload": workload, "seed": seed, "particles": g["particles"], "K": K, "iterations": iters}
@@ -117,11 +117,12 @@ def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
     t = sub.add_parser("throughput")
-    t.add_argument("--workload", default="batched", choices=["tiny", "realistic", "batched", "full", "irregular"])
+    t.add_argument("--workload", default="batched",
+                   choices=["tiny", "realistic", "batched", "full", "irregular", "crime_free"])
     t.add_argument("--particles", type=int, default=0)
     t.add_argument("--calls", type=int, default=3)
     s = sub.add_parser("surrogate")
-    s.add_argument("--workload", default="mini", choices=["mini", "realistic", "irregular"])
+    s.add_argument("--workload", default="mini", choices=["mini", "realistic", "irregular", "crime_free"])
     s.add_argument("--iters", type=int, default=30)
     s.add_argument("--seeds", default="1,2,3")
     s.add_argument("--K", type=int, default=16)

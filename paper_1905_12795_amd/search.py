@@ -25,6 +25,60 @@ def observed_data(prob, vp_true, device="cuda"):
     return fd.forward_shots(prob, torch.as_tensor(np.asarray(vp_true, np.float32), device=device))
 
 
+def lowpass(traces, dt, f_pass, f_stop, axis=1, delay=0.0):
+    """Zero-phase low-pass filter along the time axis (host, FP64), with an
+    optional delay.
+
+    Paper, Testing approach section: the observed data are filtered below
+    6 Hz. Reading: gain 1 up to f_pass, 0 from f_stop on, a raised-cosine
+    transition in between, applied in the frequency domain to each trace
+    zero-padded to at least twice its length (no wrap-around), so the
+    filter is real and even in time (no phase shift). `delay` (seconds,
+    0 <= delay < record length) multiplies by exp(-2 pi i f delay): the
+    traces of a source started `delay` later, cut to the same record.
+    """
+    x = np.asarray(traces, dtype=np.float64)
+    n = x.shape[axis]
+    if not 0.0 <= delay < n * dt:
+        raise ValueError("delay must lie in [0, record length)")
+    nfft = 1 << int(math.ceil(math.log2(2 * n)))
+    f = np.fft.rfftfreq(nfft, dt)
+    gain = np.where(f <= f_pass, 1.0, 0.0)
+    mid = (f > f_pass) & (f < f_stop)
+    gain[mid] = 0.5 * (1.0 + np.cos(np.pi * (f[mid] - f_pass) / (f_stop - f_pass)))
+    resp = gain * np.exp(-2j * np.pi * f * delay) if delay else gain
+    shape = [1] * x.ndim
+    shape[axis] = resp.size
+    spec = np.fft.rfft(x, nfft, axis=axis) * resp.reshape(shape)
+    return np.take(np.fft.irfft(spec, nfft, axis=axis), np.arange(n), axis=axis)
+
+
+def observed_data_filtered(geom, prob, vp_true, f0_obs, f_pass, f_stop, device="cuda"):
+    """Observed traces without the inverse crime: modelled on the GPU with a
+    Ricker source of peak frequency f0_obs (same grid, dt and nt as prob),
+    delayed so that its centre matches the modelling source's (Ricker delay
+    1/f0 of each), and low-passed (lowpass) on the host. The fitness models
+    with prob's own source, so even the true model keeps a non-zero misfit."""
+    g = dict(geom)
+    g["f0"] = float(f0_obs)
+    pobs = fd.Problem(g, dt=prob.dt, nt=prob.nt)
+    tr = observed_data(pobs, vp_true, device).cpu().numpy()
+    delay = 1.0 / float(geom["f0"]) - 1.0 / float(f0_obs)
+    if delay < 0:
+        raise ValueError("the observing source must have the higher peak frequency")
+    out = lowpass(tr, prob.dt, f_pass, f_stop, delay=delay).astype(np.float32)
+    return torch.as_tensor(out, device=device)
+
+
+def observed_for(geom, prob, vp_true, device="cuda"):
+    """The workload's observed data: filtered data from another source when
+    the geometry asks for it ("observed" key), else the inverse-crime data."""
+    ob = geom.get("observed")
+    if ob:
+        return observed_data_filtered(geom, prob, vp_true, ob["f0"], ob["f_pass"], ob["f_stop"], device)
+    return observed_data(prob, vp_true, device)
+
+
 def spearman(a, b):
     ra = np.argsort(np.argsort(a))
     rb = np.argsort(np.argsort(b))
