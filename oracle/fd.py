@@ -60,6 +60,14 @@ def _load():
             ctypes.c_int, ctypes.c_int, P(ctypes.c_int), P(ctypes.c_int), P(ctypes.c_double),
             P(ctypes.c_int), P(ctypes.c_double),
             P(ctypes.c_double), P(ctypes.c_double), P(ctypes.c_double)]
+        lib.oracle_gradient_run.restype = ctypes.c_int
+        lib.oracle_gradient_run.argtypes = [
+            ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+            P(ctypes.c_double), P(ctypes.c_double), P(ctypes.c_double),
+            ctypes.c_double, ctypes.c_int, P(ctypes.c_double),
+            ctypes.c_int, P(ctypes.c_int), P(ctypes.c_int), P(ctypes.c_double),
+            ctypes.c_int, ctypes.c_int, P(ctypes.c_int), P(ctypes.c_int), P(ctypes.c_double),
+            P(ctypes.c_int), P(ctypes.c_double), P(ctypes.c_double), P(ctypes.c_double)]
         _lib = lib
     return _lib
 
@@ -404,6 +412,65 @@ class Problem:
         spts = point_weights(self.src[shot], self.dz, self.dx, self.nz, self.nx, self.nbl)
         return forward_run(vel_pad, self.damp, self.dz, self.dx, self.dt, self.nt,
                            self.wavelet, spts, self.rec_pts, self.nrec)
+
+
+def gradient_run(prob, vel_pad, shot, d_obs_shot):
+    """Misfit of one shot and its gradient with respect to the padded-grid
+    velocity (discrete adjoint, oracle_fd.c). Returns (J, grad[Nz][Nx])."""
+    lib = _load()
+    w5 = np.array([float(c) for c in fd_weights(4)], dtype=np.float64)
+    vel = np.ascontiguousarray(vel_pad, dtype=np.float64)
+    dmp = np.ascontiguousarray(prob.damp, dtype=np.float64)
+    Nz, Nx = vel.shape
+    spts = point_weights(prob.src[shot], prob.dz, prob.dx, prob.nz, prob.nx, prob.nbl)
+    sI = np.array([p[0] for p in spts], dtype=np.int32)
+    sJ = np.array([p[1] for p in spts], dtype=np.int32)
+    sw = np.array([p[2] for p in spts], dtype=np.float64)
+    rp = prob.rec_pts
+    rI = np.array([p[0] for p in rp], dtype=np.int32)
+    rJ = np.array([p[1] for p in rp], dtype=np.int32)
+    rw = np.array([p[2] for p in rp], dtype=np.float64)
+    rid = np.array([p[3] for p in rp], dtype=np.int32)
+    dob = np.ascontiguousarray(d_obs_shot, dtype=np.float64)
+    wav = np.ascontiguousarray(prob.wavelet, dtype=np.float64)
+    grad = np.zeros((Nz, Nx), dtype=np.float64)
+    J = ctypes.c_double()
+    rc = lib.oracle_gradient_run(Nz, Nx, float(prob.dz), float(prob.dx), _dptr(w5), _dptr(vel), _dptr(dmp),
+                                 float(prob.dt), int(prob.nt), _dptr(wav), len(sI), _iptr(sI), _iptr(sJ),
+                                 _dptr(sw), int(prob.nrec), len(rI), _iptr(rI), _iptr(rJ), _dptr(rw),
+                                 _iptr(rid), _dptr(dob), _dptr(grad), ctypes.byref(J))
+    if rc != 0:
+        raise MemoryError("oracle_gradient_run failed")
+    return J.value, grad
+
+
+def unpad_adjoint(g_pad, nbl):
+    """Transpose of pad_edge: every padded point adds into the physical point
+    it copies."""
+    g = np.array(g_pad, dtype=np.float64)
+    if nbl == 0:
+        return g
+    g[nbl, :] += g[:nbl, :].sum(axis=0)
+    g[-nbl - 1, :] += g[-nbl:, :].sum(axis=0)
+    g = g[nbl:-nbl, :]
+    g[:, nbl] += g[:, :nbl].sum(axis=1)
+    g[:, -nbl - 1] += g[:, -nbl:].sum(axis=1)
+    return g[:, nbl:-nbl]
+
+
+def gradient(prob, vp, d_obs, shots=None, threads=None):
+    """Misfit summed over shots and its gradient with respect to the physical
+    model vp[nz][nx] (Testing approach section: the local FWI that follows
+    the global search needs the gradient of the same l2 misfit). The exact
+    gradient of the discrete misfit: pinned against central finite
+    differences of forward_shots / misfit."""
+    shots = list(range(prob.nshots)) if shots is None else list(shots)
+    vel = pad_edge(vp, prob.nbl)
+    with ThreadPoolExecutor(_workers(threads)) as ex:
+        out = list(ex.map(lambda s: gradient_run(prob, vel, s, d_obs[s]), shots))
+    J = float(sum(o[0] for o in out))
+    g_pad = np.sum([o[1] for o in out], axis=0)
+    return J, unpad_adjoint(g_pad, prob.nbl)
 
 
 def _workers(threads):

@@ -157,3 +157,42 @@ def test_planted_level_interpolation_mistake_is_caught(monkeypatch, name):
         except AssertionError:
             caught += 1
     assert caught > 0, name
+
+
+GRADIENT_MUTATIONS = {
+    "residual injected with the wrong sign": ("p0[q] += C * rw[p] * res[(size_t)k * nrec + rid[p]] / (1.0 + a);",
+                                              "p0[q] -= C * rw[p] * res[(size_t)k * nrec + rid[p]] / (1.0 + a);"),
+    "residual of the wrong time sample": ("p0[q] += C * rw[p] * res[(size_t)k * nrec + rid[p]] / (1.0 + a);",
+                                          "p0[q] += C * rw[p] * res[(size_t)(k - 1) * nrec + rid[p]] / (1.0 + a);"),
+    "adjoint without damping": ("p0[IDX(I, J)] = (2.0 * p1[IDX(I, J)] - (1.0 - a) * p2[IDX(I, J)]",
+                                "p0[IDX(I, J)] = (2.0 * p1[IDX(I, J)] - p2[IDX(I, J)]"),
+    "imaging term one level late": ("double second = (1.0 + a) * uk[q] - 2.0 * uk1[q] + (1.0 - a) * (uk2 ? uk2[q] : 0.0);",
+                                    "double second = (1.0 + a) * uk1[q] - 2.0 * (uk2 ? uk2[q] : 0.0);"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(GRADIENT_MUTATIONS))
+def test_planted_adjoint_mistake_is_caught(tmp_path, monkeypatch, name):
+    from tests import test_oracle_gradient as pins
+    old, new = GRADIENT_MUTATIONS[name]
+    assert old in SRC, name
+    src = tmp_path / "m.c"
+    src.write_text(SRC.replace(old, new, 1))
+    so = tmp_path / "m.so"
+    subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-std=c99", "-o", str(so), str(src)])
+    lib = ctypes.CDLL(str(so))
+    real = fd._load()
+    for fn in ("oracle_forward_run", "oracle_gradient_run"):
+        getattr(lib, fn).restype = ctypes.c_int
+        getattr(lib, fn).argtypes = getattr(real, fn).argtypes
+    monkeypatch.setattr(fd, "_lib", lib)
+    g, op = pins._problem()
+    vp, truth = pins._models(op)
+    dobs = fd.forward_shots(op, truth)
+    J, grad = fd.gradient(op, vp, dobs)
+    z = np.arange(op.nz)[:, None]
+    x = np.arange(op.nx)[None, :]
+    d = np.sin(0.3 * z + 1.0) * np.cos(0.2 * x + 0.5)
+    eps = 0.05
+    fd_val = (pins._phi(op, vp + eps * d, dobs) - pins._phi(op, vp - eps * d, dobs)) / (2 * eps)
+    assert abs(np.sum(grad * d) - fd_val) > 1e-4 * abs(fd_val), name
