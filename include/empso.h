@@ -237,6 +237,37 @@ int empso_time_tuning(const empso_problem *const *probs, int32_t nprob, const fl
                       empso_stream stream);
 
 /* ------------------------------------------------------------------------
+ * Misfit gradient for the local FWI that starts from the global search's best
+ * model (Testing approach section: the best EMPSO model is the starting point
+ * of a local full-waveform inversion of the same data with the same l2 misfit).
+ *
+ * The exact gradient of the discrete misfit J = 1/2 sum_s sum_n sum_r
+ * (u_s^n(x_r) - d_s^n_r)^2 with respect to the physical model, by the discrete
+ * adjoint: dividing the update by C = (v dt)^2 makes its operator symmetric,
+ * so the adjoint runs the same damped scheme backwards in time with the
+ * residuals injected at the receivers, and
+ *   dJ/dC = sum_n psi^{n+1} [(1+a) u^{n+1} - 2 u^n + (1-a) u^{n-1}] / C^2,
+ *   dJ/dv = 2 v dt^2 dJ/dC, folded onto the physical grid (an absorbing-layer
+ * point adds into the edge point it copies) and summed over all shots.
+ * Checkpointing: (u^n, u^{n-1}) are kept every K = checkpoint_every steps
+ * (0: K = ceil(sqrt(2 (nt - 1)))), and each segment is recomputed during the
+ * backward pass: about two forward passes and one adjoint pass of work, and
+ * K + 6 + 2 ceil((nt - 1)/K) fields per shot of memory.
+ * ------------------------------------------------------------------------ */
+
+/* Workspace bytes for empso_gradient (0 on invalid arguments). */
+size_t empso_gradient_workspace_bytes(const empso_problem *prob, int32_t checkpoint_every);
+
+/* Misfit and gradient of the physical model vp_d[nz][nx] (device FP32; copied
+ * once to the host for the range check, so this call waits for the stream)
+ * against obs_d[nshots][nt][nrec] (device FP32) over all shots:
+ * grad_d[nz][nx] (device FP32) = dJ/dvp, misfit_d[0] (device FP32) = J.
+ * ERANGE if a velocity lies outside [vmin, vmax]; EINVAL for NULL arguments,
+ * nt < 2 or a negative interval; EWORKSPACE if ws_bytes is too small. */
+int empso_gradient(const empso_problem *prob, const float *vp_d, const float *obs_d, float *grad_d,
+                   float *misfit_d, int32_t checkpoint_every, void *ws, size_t ws_bytes, empso_stream stream);
+
+/* ------------------------------------------------------------------------
  * Surrogate network (not part of the paper): maps control-node velocities to
  * a standardised log-misfit so that candidates can be ranked before the
  * finite-difference fitness. x_hat = (x - lo)/(hi - lo); three hidden layers

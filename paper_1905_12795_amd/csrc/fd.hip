@@ -1441,3 +1441,327 @@ extern "C" int empso_autotune_fitness(const empso_problem *const *probs, int32_t
     if (best_us_per_step) *best_us_per_step = best_us;
     return EMPSO_OK;
 }
+
+// ---------------------------------------------------------------------------
+// Misfit gradient (the local FWI that follows the global search, Testing
+// approach section), by the discrete adjoint of the scheme with checkpoints.
+//
+// Dividing the update by C = (v dt)^2 makes its operator symmetric, so the
+// adjoint psi runs the same damped scheme backwards in time with the residual
+// r^k = u^k - d^k injected at the receivers:
+//   (1+a) psi^k = 2 psi^{k+1} - (1-a) psi^{k+2} + C (Lap_h psi^{k+1} + r^k),
+// k = nt-1 .. 1, psi^{nt} = psi^{nt+1} = 0, and
+//   dJ/dC = sum_n psi^{n+1} [(1+a) u^{n+1} - 2 u^n + (1-a) u^{n-1}] / C^2,
+//   dJ/dv = dJ/dC 2 v dt^2, folded from the padded grid onto the physical
+// model (each padded point adds into the point it copies) and summed over
+// shots. Both directions use the increment form of the fitness kernels. The
+// forward pass keeps (u^{jK}, u^{jK-1}) every K steps; the backward pass
+// restores each segment from its checkpoint, recomputes its K time levels and
+// runs the adjoint through it, accumulating the gradient as it goes.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct GradRun {
+    float *fields;              // the run's fields, gfs floats apart
+    const float *obs;           // [nt][nrec]
+    double *acc;                // [nrec] sum of squared residuals over k >= 1
+    int srcS, srcC;             // stored row and column of the source
+};
+
+struct GradShared {
+    const float *C, *az, *ax, *wav;
+    const int *recmap;
+    size_t gfs;                 // floats per field
+    int Nz, Nx, S, nrec, recS, nt;
+    float cz1, cz2, cz3, cz4, cx1, cx2, cx3, cx4, wscale;
+};
+
+// Field slots of a run: 0 .. K+1 segment levels (the forward pass uses 0..2
+// as a ring), K+2 .. K+4 adjoint ring, K+5 gradient accumulator, then two per
+// checkpoint.
+struct GradSlots {
+    int K, ncheck;
+    int seg(int i) const { return i; }
+    int adj(int k) const { return K + 2 + ((k % 3) + 3) % 3; }
+    int gacc() const { return K + 5; }
+    int ck(int j, int which) const { return K + 6 + 2 * j + which; }
+    int total() const { return K + 6 + 2 * ncheck; }
+};
+
+static int grad_interval(const empso_problem *p, int K) {
+    if (K > 0) return K;
+    return std::max(1, (int)std::ceil(std::sqrt(2.0 * std::max(1, p->g.nt - 1))));
+}
+
+// One time step of every run: out = cur + d with
+// d = [(1-a)(cur - prev) + C (Lap cur + s)] / (1+a). Forward (ADJ = false):
+// s = fsrc at the source point. Adjoint (ADJ = true): s = u^k - d^k at the
+// receivers (accumulated into the misfit), and the gradient accumulator takes
+// out * [(1+a)(u^k - u^{k-1}) - (1-a)(u^{k-1} - u^{k-2})].
+// Thread (x, y) of block (bx, by, run) updates columns 4 (64 bx + x) .. +3 of
+// padded row 4 by + y.
+template <bool ADJ, bool ISO>
+__global__ __launch_bounds__(256) void k_gstep(const GradRun *__restrict__ runs, const GradShared sh, int cur,
+                                               int prev, int out, float fsrc, int k, int uk, int uk1, int uk2,
+                                               int gacc) {
+    const int I = blockIdx.y * 4 + (int)threadIdx.y;
+    const int J0 = 4 * (blockIdx.x * 64 + (int)threadIdx.x);
+    if (I >= sh.Nz || J0 >= sh.Nx) return;
+    const GradRun R = runs[blockIdx.z];
+    const int s = I + kRing, c = J0 + kRing;
+    const size_t o = (size_t)s * sh.S + c;
+    const float *Fc = R.fields + (size_t)cur * sh.gfs;
+    const float *Fp = R.fields + (size_t)prev * sh.gfs;
+    auto ld4 = [&](const float *F, size_t off) { return *reinterpret_cast<const float4 *>(F + off); };
+    const float4 cl = ld4(Fc, o - 4), cc = ld4(Fc, o), cr = ld4(Fc, o + 4);
+    const float v[12] = {cl.x, cl.y, cl.z, cl.w, cc.x, cc.y, cc.z, cc.w, cr.x, cr.y, cr.z, cr.w};
+    float4 zp[4], zm[4];
+#pragma unroll
+    for (int m = 1; m <= 4; ++m) {
+        zm[m - 1] = ld4(Fc, o - (size_t)m * sh.S);
+        zp[m - 1] = ld4(Fc, o + (size_t)m * sh.S);
+    }
+    const float4 pv4 = ld4(Fp, o), C4 = ld4(sh.C, o);
+    const float pv[4] = {pv4.x, pv4.y, pv4.z, pv4.w}, Cv[4] = {C4.x, C4.y, C4.z, C4.w};
+    const float cz[4] = {sh.cz1, sh.cz2, sh.cz3, sh.cz4}, cx[4] = {sh.cx1, sh.cx2, sh.cx3, sh.cx4};
+    const float azr = sh.az[I];
+    float4 Uk4, Uk14, Uk24;
+    if (ADJ) {
+        Uk4 = ld4(R.fields + (size_t)uk * sh.gfs, o);
+        Uk14 = ld4(R.fields + (size_t)uk1 * sh.gfs, o);
+        Uk24 = ld4(R.fields + (size_t)uk2 * sh.gfs, o);
+    }
+    const float ukv[4] = {ADJ ? Uk4.x : 0.f, ADJ ? Uk4.y : 0.f, ADJ ? Uk4.z : 0.f, ADJ ? Uk4.w : 0.f};
+    float res[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const float u = v[4 + q];
+        const float zs[4] = {(&zp[3].x)[q] + (&zm[3].x)[q], (&zp[2].x)[q] + (&zm[2].x)[q],
+                             (&zp[1].x)[q] + (&zm[1].x)[q], (&zp[0].x)[q] + (&zm[0].x)[q]};
+        const float xs[4] = {v[q] + v[8 + q], v[1 + q] + v[7 + q], v[2 + q] + v[6 + q], v[3 + q] + v[5 + q]};
+        float lap;
+        if (ISO) {
+            lap = cz[3] * fmaf(-4.0f, u, zs[0] + xs[0]);
+            lap = fmaf(cz[2], fmaf(-4.0f, u, zs[1] + xs[1]), lap);
+            lap = fmaf(cz[1], fmaf(-4.0f, u, zs[2] + xs[2]), lap);
+            lap = fmaf(cz[0], fmaf(-4.0f, u, zs[3] + xs[3]), lap);
+        } else {
+            lap = cz[3] * fmaf(-2.0f, u, zs[0]);
+            lap = fmaf(cz[2], fmaf(-2.0f, u, zs[1]), lap);
+            lap = fmaf(cz[1], fmaf(-2.0f, u, zs[2]), lap);
+            lap = fmaf(cz[0], fmaf(-2.0f, u, zs[3]), lap);
+            lap = fmaf(cx[3], fmaf(-2.0f, u, xs[0]), lap);
+            lap = fmaf(cx[2], fmaf(-2.0f, u, xs[1]), lap);
+            lap = fmaf(cx[1], fmaf(-2.0f, u, xs[2]), lap);
+            lap = fmaf(cx[0], fmaf(-2.0f, u, xs[3]), lap);
+        }
+        const int J = J0 + q;
+        res[q] = 0.0f;
+        if (!ADJ) {
+            if (s == R.srcS && c + q == R.srcC) lap += fsrc;
+        } else if (s == sh.recS && J < sh.Nx) {
+            const int r = sh.recmap[J];
+            if (r >= 0) {
+                res[q] = ukv[q] - R.obs[(size_t)k * sh.nrec + r];
+                lap += res[q];
+                R.acc[r] += (double)res[q] * (double)res[q];
+            }
+        }
+        (void)res;
+        const float a = azr + ((J < sh.Nx) ? sh.ax[J] : 0.0f);
+        const float d = fmaf(Cv[q], lap, (1.0f - a) * (u - pv[q])) * __builtin_amdgcn_rcpf(1.0f + a);
+        const float un = u + d;
+        R.fields[(size_t)out * sh.gfs + o + q] = un;
+        if (ADJ) {
+            const float u0 = (&Uk4.x)[q], u1 = (&Uk14.x)[q], u2 = (&Uk24.x)[q];
+            float *g = R.fields + (size_t)gacc * sh.gfs + o + q;
+            *g = fmaf(un, (1.0f + a) * (u0 - u1) - (1.0f - a) * (u1 - u2), *g);
+        }
+    }
+}
+
+__global__ void k_gcopy(const GradRun *__restrict__ runs, size_t gfs, int src, int dst) {
+    const GradRun R = runs[blockIdx.y];
+    const float4 *a = reinterpret_cast<const float4 *>(R.fields + (size_t)src * gfs);
+    float4 *b = reinterpret_cast<float4 *>(R.fields + (size_t)dst * gfs);
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < gfs / 4; i += (size_t)gridDim.x * blockDim.x)
+        b[i] = a[i];
+}
+
+// Physical gradient: each physical point gathers the padded points that copy
+// it (its own, plus the absorbing-layer strip or corner beyond an edge), over
+// all runs in a fixed order, times 2 / (v^3 dt^2).
+__global__ void k_gfold(const GradRun *__restrict__ runs, int nruns, const GradShared sh, int gacc, const float *vp,
+                        int nz, int nx, int nbl, double dt, float *grad) {
+    const int64_t n = (int64_t)nz * nx;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(q / nx), j = (int)(q - (int64_t)i * nx);
+        const int I0 = i == 0 ? 0 : i + nbl, I1 = i == nz - 1 ? sh.Nz - 1 : i + nbl;
+        const int J0 = j == 0 ? 0 : j + nbl, J1 = j == nx - 1 ? sh.Nx - 1 : j + nbl;
+        double sum = 0.0;
+        for (int r = 0; r < nruns; ++r) {
+            const float *g = runs[r].fields + (size_t)gacc * sh.gfs;
+            for (int I = I0; I <= I1; ++I)
+                for (int J = J0; J <= J1; ++J) sum += (double)g[(size_t)(I + kRing) * sh.S + J + kRing];
+        }
+        const double v = vp[q];
+        grad[q] = (float)(sum * 2.0 / (v * v * v * dt * dt));
+    }
+}
+
+// J = 1/2 sum over runs and receivers of (sum_{k>=1} r^k^2 + d^0^2) (u^0 = 0).
+__global__ __launch_bounds__(256) void k_gmisfit(const GradRun *__restrict__ runs, int nruns, int nrec, float *out) {
+    double s = 0.0;
+    for (int r = 0; r < nruns; ++r)
+        for (int q = threadIdx.x; q < nrec; q += blockDim.x) {
+            const double d0 = runs[r].obs[q];
+            s += runs[r].acc[q] + d0 * d0;
+        }
+    __shared__ double red[256];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = (float)(0.5 * red[0]);
+}
+
+struct GradLayout {
+    GradSlots sl;
+    size_t fb, runs_off, cd_off, acc_off, C_off, fields_off, total;
+};
+
+static GradLayout grad_layout(const empso_problem *p, int K) {
+    GradLayout L;
+    L.sl.K = grad_interval(p, K);
+    L.sl.ncheck = (std::max(1, p->g.nt - 1) - 1) / L.sl.K + 1;     // checkpoints at 0, K, .. <= nt - 2
+    L.fb = field_bytes(p);
+    size_t k = 0;
+    auto take = [&](size_t b) { size_t r = k; k = align_up(k + b, 256); return r; };
+    const int ns = p->g.nshots;
+    L.runs_off = take(sizeof(GradRun) * ns);
+    L.cd_off = take(sizeof(CoefDesc));
+    L.acc_off = take(sizeof(double) * (size_t)ns * p->g.nrec);
+    L.C_off = take(L.fb);
+    L.fields_off = take(L.fb * (size_t)L.sl.total() * ns);
+    L.total = k;
+    return L;
+}
+
+}  // namespace
+
+extern "C" size_t empso_gradient_workspace_bytes(const empso_problem *p, int32_t checkpoint_every) {
+    if (!p || checkpoint_every < 0) return 0;
+    return grad_layout(p, checkpoint_every).total;
+}
+
+extern "C" int empso_gradient(const empso_problem *p, const float *vp_d, const float *obs_d, float *grad_d,
+                              float *misfit_d, int32_t checkpoint_every, void *ws, size_t ws_bytes,
+                              empso_stream stream) {
+    clear_error();
+    if (!p || !vp_d || !obs_d || !grad_d || !misfit_d || !ws) EMPSO_FAIL(EMPSO_EINVAL, "NULL argument");
+    if (checkpoint_every < 0) EMPSO_FAIL(EMPSO_EINVAL, "checkpoint_every must be >= 0");
+    if (p->g.nt < 2) EMPSO_FAIL(EMPSO_EINVAL, "the gradient needs nt >= 2");
+    if (reinterpret_cast<uintptr_t>(ws) % 256) EMPSO_FAIL(EMPSO_EINVAL, "workspace must be 256-byte aligned");
+    const GradLayout L = grad_layout(p, checkpoint_every);
+    if (ws_bytes < L.total) EMPSO_FAIL(EMPSO_EWORKSPACE, "workspace %zu < %zu bytes", ws_bytes, L.total);
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<float> vh((size_t)p->g.nz * p->g.nx);
+    EMPSO_HIP(hipMemcpyAsync(vh.data(), vp_d, vh.size() * sizeof(float), hipMemcpyDeviceToHost, st));
+    EMPSO_HIP(hipStreamSynchronize(st));
+    for (size_t k = 0; k < vh.size(); ++k)
+        if (!(vh[k] >= (float)p->g.vmin && vh[k] <= (float)p->g.vmax) || !std::isfinite(vh[k]))
+            EMPSO_FAIL(EMPSO_ERANGE, "vp[%zu] = %g outside [%g, %g]", k, (double)vh[k], p->g.vmin, p->g.vmax);
+
+    unsigned char *w = reinterpret_cast<unsigned char *>(ws);
+    const int ns = p->g.nshots, nt = p->g.nt;
+    const GradSlots &sl = L.sl;
+    const size_t gfs = L.fb / sizeof(float);
+    std::vector<GradRun> hr(ns);
+    for (int s = 0; s < ns; ++s) {
+        hr[s].fields = reinterpret_cast<float *>(w + L.fields_off + L.fb * (size_t)sl.total() * s);
+        hr[s].obs = obs_d + (size_t)s * nt * p->g.nrec;
+        hr[s].acc = reinterpret_cast<double *>(w + L.acc_off) + (size_t)s * p->g.nrec;
+        hr[s].srcS = p->srcI[s] + kRing;
+        hr[s].srcC = p->srcJ[s] + kRing;
+    }
+    GradRun *runs = reinterpret_cast<GradRun *>(w + L.runs_off);
+    EMPSO_HIP(hipMemcpy(runs, hr.data(), sizeof(GradRun) * ns, hipMemcpyHostToDevice));
+    GradShared sh;
+    sh.C = reinterpret_cast<const float *>(w + L.C_off);
+    sh.az = p->d_az; sh.ax = p->d_ax; sh.wav = p->d_wav; sh.recmap = p->d_recmap;
+    sh.gfs = gfs;
+    sh.Nz = p->Nz; sh.Nx = p->Nx; sh.S = p->S; sh.nrec = p->g.nrec; sh.recS = p->recI + kRing; sh.nt = nt;
+    sh.cz1 = p->cz[0]; sh.cz2 = p->cz[1]; sh.cz3 = p->cz[2]; sh.cz4 = p->cz[3];
+    sh.cx1 = p->cx[0]; sh.cx2 = p->cx[1]; sh.cx3 = p->cx[2]; sh.cx4 = p->cx[3];
+    sh.wscale = p->wscale;
+    const bool iso = p->g.dz == p->g.dx;
+
+    // clear the fields and accumulators, then the coefficient field of vp
+    const size_t zero_bytes = L.total - L.acc_off;
+    k_zero<<<1024, 256, 0, st>>>(reinterpret_cast<float4 *>(w + L.acc_off), (int64_t)(zero_bytes / 16));
+    CoefDesc cd = {};
+    cd.C = reinterpret_cast<float *>(w + L.C_off);
+    cd.vp = vp_d;
+    cd.map = node_map(p);
+    cd.nz = p->g.nz; cd.nx = p->g.nx; cd.nbl = p->g.nbl; cd.Nz = p->Nz; cd.Nx = p->Nx; cd.S = p->S;
+    cd.dt = (float)p->g.dt;
+    CoefDesc *cdd = reinterpret_cast<CoefDesc *>(w + L.cd_off);
+    EMPSO_HIP(hipMemcpy(cdd, &cd, sizeof(CoefDesc), hipMemcpyHostToDevice));
+    k_coef<<<dim3(1024, 1), 256, 0, st>>>(cdd);
+
+    const dim3 blk(64, 4), grd((p->Nx + 255) / 256, (p->Nz + 3) / 4, ns);
+    const int cblocks = (int)std::min<size_t>(4096, (gfs / 4 + 255) / 256);
+    // the source value of step n is wavelet[n] / (dz dx), read on the host
+    std::vector<float> wav(nt);
+    EMPSO_HIP(hipMemcpy(wav.data(), p->d_wav, sizeof(float) * nt, hipMemcpyDeviceToHost));
+    auto step_fwd = [&](int n, int cur, int prev, int out) {
+        const float fs = wav[n] * p->wscale;
+        if (iso)
+            k_gstep<false, true><<<grd, blk, 0, st>>>(runs, sh, cur, prev, out, fs, n, 0, 0, 0, 0);
+        else
+            k_gstep<false, false><<<grd, blk, 0, st>>>(runs, sh, cur, prev, out, fs, n, 0, 0, 0, 0);
+    };
+    auto step_adj = [&](int k, int cur, int prev, int out, int uk, int uk1, int uk2) {
+        if (iso)
+            k_gstep<true, true><<<grd, blk, 0, st>>>(runs, sh, cur, prev, out, 0.0f, k, uk, uk1, uk2, sl.gacc());
+        else
+            k_gstep<true, false><<<grd, blk, 0, st>>>(runs, sh, cur, prev, out, 0.0f, k, uk, uk1, uk2, sl.gacc());
+    };
+    auto copy = [&](int src, int dst) { k_gcopy<<<dim3(cblocks, ns), 256, 0, st>>>(runs, gfs, src, dst); };
+
+    // forward pass over n = 0 .. nt-2 with u^n in ring slot (n mod 3); the
+    // checkpoint j holds (u^{jK}, u^{jK-1}) for every jK <= nt - 2
+    const int K = sl.K, last = sl.ncheck - 1;
+    auto ring = [](int n) { return ((n % 3) + 3) % 3; };
+    for (int n = 0; n < last * K; ++n) {
+        step_fwd(n, ring(n), ring(n - 1), ring(n + 1));
+        if ((n + 1) % K == 0) {
+            const int j = (n + 1) / K;
+            copy(ring(n + 1), sl.ck(j, 0));
+            copy(ring(n), sl.ck(j, 1));
+        }
+    }
+    // backward pass, segment by segment: segment j covers u^{jK-1} .. u^{e}
+    // in slots 0 .. e - jK + 1 (checkpoint 0 is the zero initial state)
+    for (int j = last; j >= 0; --j) {
+        const int b = j * K, e = std::min((j + 1) * K, nt - 1);
+        if (j > 0) {
+            copy(sl.ck(j, 1), sl.seg(0));
+            copy(sl.ck(j, 0), sl.seg(1));
+        } else {
+            copy(sl.ck(0, 1), sl.seg(0));                 // zero fields
+            copy(sl.ck(0, 0), sl.seg(1));
+        }
+        for (int n = b; n < e; ++n) step_fwd(n, sl.seg(n - b + 1), sl.seg(n - b), sl.seg(n - b + 2));
+        for (int k = e; k >= b + 1; --k)
+            step_adj(k, sl.adj(k + 1), sl.adj(k + 2), sl.adj(k), sl.seg(k - b + 1), sl.seg(k - b), sl.seg(k - b - 1));
+    }
+    const int64_t npts = (int64_t)p->g.nz * p->g.nx;
+    k_gfold<<<(int)std::min<int64_t>(2048, (npts + 255) / 256), 256, 0, st>>>(runs, ns, sh, sl.gacc(), vp_d, p->g.nz,
+                                                                              p->g.nx, p->g.nbl, p->g.dt, grad_d);
+    k_gmisfit<<<1, 256, 0, st>>>(runs, ns, p->g.nrec, misfit_d);
+    EMPSO_HIP(hipGetLastError());
+    return EMPSO_OK;
+}

@@ -1,0 +1,140 @@
+"""GPU misfit gradient (discrete adjoint with checkpoints) against the FP64
+oracle's (run on an MI355X).
+
+Bar: the forward traces and misfits carry the 2e-4 FP32 bar; the gradient is a
+time sum of products of a forward and an adjoint field, each within that bar,
+so it is held to 1e-3 relative L2 against the oracle. Checkpoint intervals
+change only the schedule, so every interval gives the same bits; data made
+by the fitness path's own kernels give an exactly zero residual and gradient.
+"""
+import copy
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import fd as ofd
+from workloads.configs import config, true_model
+
+pytestmark = pytest.mark.gpu
+
+REL_G = 1e-3
+REL = 2e-4
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def gfd():
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    from paper_1905_12795_amd import fd
+    return fd
+
+
+def _tiny():
+    g = copy.deepcopy(config("tiny"))
+    g.update(nz=21, nx=31, nbl=6, tmax=0.25, f0=15.0, ncz=2, ncx=3)
+    g["src"] = [[0.0, 100.0], [50.0, 230.0]]
+    g["rec"] = [[0.0, 10.0 * j] for j in range(0, 31, 3)]
+    return g
+
+
+def _wide():
+    """Several x tiles, a ragged z tail, two shots, receivers every other column."""
+    g = copy.deepcopy(config("tiny"))
+    g.update(nz=61, nx=301, nbl=40, tmax=0.3, ncz=3, ncx=4)
+    g["src"] = [[0.0, 1000.0], [20.0, 2230.0]]
+    g["rec"] = [[0.0, 10.0 * j] for j in range(0, 301, 2)]
+    return g
+
+
+def _models(nz, nx, dz, dx):
+    z = np.arange(nz)[:, None] * dz
+    x = np.arange(nx)[None, :] * dx
+    vp = 1800.0 + 600.0 * z / z.max() + 80.0 * np.sin(x / 90.0)        # below the 2700 m/s vmax
+    truth = vp + 150.0 * np.exp(-((z - 0.5 * z.max()) ** 2 + (x - 0.55 * x.max()) ** 2) / (0.05 * (x.max() ** 2)))
+    return vp, truth
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("geom", [_tiny, _wide])
+def test_gradient_matches_oracle_and_checkpointing_is_invariant(gfd, geom):
+    g = geom()
+    op = ofd.Problem(g)
+    gp = gfd.Problem(g, dt=op.dt, nt=op.nt)
+    vp, truth = _models(op.nz, op.nx, op.dz, op.dx)
+    dobs = ofd.forward_shots(op, truth)
+    Jo, go = ofd.gradient(op, vp.astype(np.float32).astype(np.float64), dobs)
+    vpt = torch.tensor(vp, dtype=torch.float32, device="cuda")
+    obs = torch.tensor(dobs.astype(np.float32), device="cuda")
+    ref = None
+    for K in (0, 1, 7, op.nt):
+        mis, grad = gfd.gradient(gp, vpt, obs, checkpoint_every=K)
+        if ref is None:
+            ref = (mis.clone(), grad.clone())
+            e = _rel(grad.cpu().numpy(), go)
+            _say(geom.__name__, "nt", op.nt, "gradient rel L2", e, "misfit", float(mis), Jo)
+            assert e <= REL_G
+            assert float(mis) == pytest.approx(Jo, rel=REL)
+        else:
+            assert torch.equal(mis, ref[0]) and torch.equal(grad, ref[1]), K
+
+
+def test_data_from_the_fitness_kernels_give_zero_residual(gfd):
+    g = _wide()
+    gp = gfd.Problem(g)
+    vp, _ = _models(g["nz"], g["nx"], g["dz"], g["dx"])
+    vpt = torch.tensor(vp, dtype=torch.float32, device="cuda")
+    obs = gfd.forward_shots(gp, vpt)
+    mis, grad = gfd.gradient(gp, vpt, obs)
+    assert float(mis) == 0.0
+    assert torch.count_nonzero(grad).item() == 0
+
+
+def test_gradient_misfit_equals_fitness_of_the_same_model(gfd):
+    g = _wide()
+    gp = gfd.Problem(g)
+    rng = np.random.default_rng(3)
+    X = rng.uniform(1500, 2600, (1, 12))
+    vpt = gfd.vp_from_nodes(gp, torch.tensor(X, dtype=torch.float32, device="cuda"))[0].contiguous()
+    _, truth = _models(g["nz"], g["nx"], g["dz"], g["dx"])
+    obs = gfd.forward_shots(gp, torch.tensor(truth, dtype=torch.float32, device="cuda"))
+    f = float(gfd.FitnessBatch([gp], [obs], [0])(X)[0])
+    mis, _ = gfd.gradient(gp, vpt, obs)
+    assert float(mis) == pytest.approx(f, rel=1e-6)
+
+
+@pytest.mark.timeout(600)
+def test_realistic_full_size_directional_derivative(gfd):
+    """At the benchmark's full size (16 shots, nt = 8114) the oracle cannot keep
+    every time level, so the gradient is checked against central differences
+    of the GPU misfit itself along a smooth direction (FP32 misfits, FP64
+    sums: a 1e-2 bar)."""
+    import time
+    g = config("realistic")
+    gp = gfd.Problem(g)
+    truth = true_model(g)
+    obs = gfd.forward_shots(gp, torch.tensor(truth, dtype=torch.float32, device="cuda"))
+    z = np.arange(g["nz"])[:, None] * g["dz"]
+    x = np.arange(g["nx"])[None, :] * g["dx"]
+    vp = 1500.0 + 4000.0 * z / z.max() + 0 * x
+    vpt = torch.tensor(vp, dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.time()
+    mis, grad = gfd.gradient(gp, vpt, obs)
+    torch.cuda.synchronize()
+    _say("realistic gradient %.2fs, misfit %.6g" % (time.time() - t0, float(mis)))
+    d = torch.tensor(np.sin(z / 400.0) * np.cos(x / 900.0), dtype=torch.float32, device="cuda")
+    eps = 20.0
+    mp, _ = gfd.gradient(gp, vpt + eps * d, obs)
+    mm, _ = gfd.gradient(gp, vpt - eps * d, obs)
+    fd_val = (float(mp) - float(mm)) / (2 * eps)
+    dot = float(torch.sum(grad.double() * d.double()))
+    _say("directional derivative: adjoint %.6g, central difference %.6g" % (dot, fd_val))
+    assert dot == pytest.approx(fd_val, rel=1e-2)

@@ -121,3 +121,8 @@ def test_empty_batch_is_a_no_op(L):
     assert L.lib.empso_fitness_batch(None, 1, None, None, -1, None, 1, None, None, 0, None, None) == -1
     assert L.lib.empso_fitness_workspace_bytes(None, 1, None, 0) == 0
     assert L.lib.empso_forward_shots(None, None, 0, 0, None, None, 0, None, None) == -1      # no problem
+
+
+def test_gradient_null_arguments(L):
+    assert L.lib.empso_gradient_workspace_bytes(None, 0) == 0
+    assert L.lib.empso_gradient(None, None, None, None, None, 0, None, 0, None) == -1
