@@ -113,6 +113,25 @@ def surrogate(workload, iters, seeds, K, log):
     _emit(summ)
 
 
+def local_fwi(workload, search_iters, fwi_iters, seed):
+    """The paper's workflow: the EMPSO best model starts a local FWI of the same data."""
+    from paper_1905_12795_amd import fwi
+    g = config(workload)
+    prob = fd.Problem(g)
+    truth = true_model(g)
+    dobs = search.observed_for(g, prob, truth)
+    h = search.run(g, dobs, prob, search_iters, "plain", seed=seed)
+    _emit({"stage": "empso", "iterations": search_iters, "best": h[-1]["best"], "wall_s": h[-1]["wall_s"]})
+    best = np.asarray(h[-1]["best_position"], dtype=np.float32)
+    v0 = fd.vp_from_nodes(prob, torch.tensor(best[None, :], device="cuda"))[0].contiguous()
+    t0 = time.perf_counter()
+    v, hist = fwi.invert(prob, dobs, v0, fwi_iters, log=lambda r: _emit({"stage": "fwi", **r}))
+    torch.cuda.synchronize()
+    _emit({"workload": workload, "seed": seed, "empso_misfit": h[-1]["best"], "fwi_misfit": hist[-1]["misfit"],
+           "fwi_iterations": len(hist) - 1, "fwi_wall_s": time.perf_counter() - t0,
+           "rms_error_empso": fwi.rms_error(v0.cpu().numpy(), truth), "rms_error_fwi": fwi.rms_error(v, truth)})
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -127,9 +146,16 @@ def main():
     s.add_argument("--seeds", default="1,2,3")
     s.add_argument("--K", type=int, default=16)
     s.add_argument("--log", default=None)
+    f = sub.add_parser("fwi")
+    f.add_argument("--workload", default="realistic", choices=["realistic", "irregular", "crime_free"])
+    f.add_argument("--search-iters", type=int, default=15)
+    f.add_argument("--fwi-iters", type=int, default=10)
+    f.add_argument("--seed", type=int, default=1)
     a = ap.parse_args()
     if a.cmd == "throughput":
         throughput(a.workload, a.particles, a.calls)
+    elif a.cmd == "fwi":
+        local_fwi(a.workload, a.search_iters, a.fwi_iters, a.seed)
     else:
         surrogate(a.workload, a.iters, [int(x) for x in a.seeds.split(",")], a.K, a.log)
 

@@ -84,6 +84,7 @@ class Problem:
         g.rec_zx = self._rec.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         g.ncz, g.ncx = int(geom.get("ncz", 0)), int(geom.get("ncx", 0))
         g.vmin, g.vmax = float(vmin), float(geom["vmax"])
+        self.vmin, self.vmax = g.vmin, g.vmax           # the velocity bounds the library enforces
         g.damp_R = float(geom.get("damp_R", 1e-3))
         if geom.get("node_z") is not None:          # layered node grid
             self._nz_ = np.ascontiguousarray(np.asarray(geom["node_z"], dtype=np.float64))

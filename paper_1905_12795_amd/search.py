@@ -90,6 +90,7 @@ def run(geom, dobs, prob, iterations, mode="plain", seed=0, K=16, warmup=2, sur_
     """Run the search; returns the list of per-iteration records.
 
     Record fields: iteration, best, mean, median, evaluations (FD, cumulative),
+    best_position (last record only: the global best's node values),
     wall_s (cumulative, FD + host + surrogate), and in screened mode
     surrogate_rho (Spearman correlation between the surrogate's prediction and
     the FD misfit of the evaluated particles, measured before it trains on
@@ -139,6 +140,8 @@ def run(geom, dobs, prob, iterations, mode="plain", seed=0, K=16, warmup=2, sur_
             break
     if logf:
         logf.close()
+    if out:
+        out[-1]["best_position"] = [float(x) for x in swarm.g]     # gbest nodes (FP64), not logged
     return out
 
 

@@ -138,3 +138,17 @@ def test_realistic_full_size_directional_derivative(gfd):
     dot = float(torch.sum(grad.double() * d.double()))
     _say("directional derivative: adjoint %.6g, central difference %.6g" % (dot, fd_val))
     assert dot == pytest.approx(fd_val, rel=1e-2)
+
+
+def test_local_fwi_reduces_misfit_and_model_error(gfd):
+    from paper_1905_12795_amd import fwi
+    g = _wide()
+    gp = gfd.Problem(g)
+    vp, truth = _models(g["nz"], g["nx"], g["dz"], g["dx"])
+    obs = gfd.forward_shots(gp, torch.tensor(truth, dtype=torch.float32, device="cuda"))
+    v, hist = fwi.invert(gp, obs, vp, 8)
+    J = [h["misfit"] for h in hist]
+    _say("local FWI misfits", J, "rms model error", fwi.rms_error(vp, truth), "->", fwi.rms_error(v, truth))
+    assert all(b <= a for a, b in zip(J, J[1:]))
+    assert J[-1] < 0.5 * J[0]
+    assert fwi.rms_error(v, truth) < fwi.rms_error(vp, truth)
