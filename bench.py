@@ -89,6 +89,33 @@ def cpu_baseline(geom, dt, nt, threads, steps):
             "gpt_updates_per_s": rate / 1e9, "seconds": el}
 
 
+def gradient_report(prob, dobs, reps=3):
+    """Misfit gradient of a smooth starting model over the same 16 shots
+    (outside the timed region): seconds per gradient with HIP events, and the
+    point-update rate of its three passes (forward with checkpoints, segment
+    recomputation, adjoint)."""
+    import torch
+
+    from paper_1905_12795_amd import fd
+
+    nz, nx = prob.info.nz, prob.info.nx
+    z = np.arange(nz, dtype=np.float64)[:, None] / (nz - 1)
+    v0 = torch.tensor(np.repeat(1500.0 + 4000.0 * z, nx, axis=1), dtype=torch.float32, device="cuda")
+    ws = fd.workspace(fd.lib.empso_gradient_workspace_bytes(prob.handle, 0))
+    fd.gradient(prob, v0, dobs, 0, ws)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        mis, _g = fd.gradient(prob, v0, dobs, 0, ws)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1000.0 / reps
+    upd = 3 * prob.updates_per_run * prob.nshots
+    return {"workload": "realistic geometry, 16 shots, nt %d, a linear 1500-5500 m/s starting model" % prob.nt,
+            "seconds_per_gradient": sec, "gpt_updates_per_s_three_passes": upd / sec / 1e9,
+            "misfit": float(mis), "workspace_gib": ws.numel() / 2 ** 30}
+
+
 def _strict(v):
     """The result with non-finite floats replaced by None (strict JSON)."""
     if isinstance(v, dict):
@@ -160,6 +187,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate-vs-plain report")
+    ap.add_argument("--no-gradient", action="store_true", help="skip the misfit-gradient report")
     ap.add_argument("--cpu-steps", type=int, default=0,
                     help="time steps of the oracle sample (0: the whole record, one complete evaluation)")
     ap.add_argument("--bz", type=int, default=None, help="fix the tile height (default: autotune)")
@@ -252,6 +280,8 @@ def main():
                      "avg_launch_us": launch_s * 1e6, "isolated_launch_us": iso_us_step * T,
                      "measured_frac": None if traffic is None else traffic / launch_s / 1e9 / HBM_PEAK_GBS},
     }
+    if not args.no_gradient:
+        out["gradient"] = gradient_report(prob, dobs)
     if not args.no_surrogate:
         out["surrogate"] = surrogate_report()
     if not args.no_cpu_baseline:

@@ -252,7 +252,9 @@ int empso_time_tuning(const empso_problem *const *probs, int32_t nprob, const fl
  * Checkpointing: (u^n, u^{n-1}) are kept every K = checkpoint_every steps
  * (0: K = ceil(sqrt(2 (nt - 1)))), and each segment is recomputed during the
  * backward pass: about two forward passes and one adjoint pass of work, and
- * K + 6 + 2 ceil((nt - 1)/K) fields per shot of memory.
+ * K + 7 + 2 ceil((nt - 1)/K) fields per shot of memory. The same pass can
+ * return the source illumination sum_s sum_{n>=1} u_s^n(x)^2, folded the same
+ * way, the usual diagonal scaling (pseudo-Hessian) of the gradient.
  * ------------------------------------------------------------------------ */
 
 /* Workspace bytes for empso_gradient (0 on invalid arguments). */
@@ -261,11 +263,13 @@ size_t empso_gradient_workspace_bytes(const empso_problem *prob, int32_t checkpo
 /* Misfit and gradient of the physical model vp_d[nz][nx] (device FP32; copied
  * once to the host for the range check, so this call waits for the stream)
  * against obs_d[nshots][nt][nrec] (device FP32) over all shots:
- * grad_d[nz][nx] (device FP32) = dJ/dvp, misfit_d[0] (device FP32) = J.
+ * grad_d[nz][nx] (device FP32) = dJ/dvp, misfit_d[0] (device FP32) = J,
+ * illum_d[nz][nx] (device FP32, may be NULL) = the source illumination.
  * ERANGE if a velocity lies outside [vmin, vmax]; EINVAL for NULL arguments,
  * nt < 2 or a negative interval; EWORKSPACE if ws_bytes is too small. */
 int empso_gradient(const empso_problem *prob, const float *vp_d, const float *obs_d, float *grad_d,
-                   float *misfit_d, int32_t checkpoint_every, void *ws, size_t ws_bytes, empso_stream stream);
+                   float *misfit_d, float *illum_d, int32_t checkpoint_every, void *ws, size_t ws_bytes,
+                   empso_stream stream);
 
 /* ------------------------------------------------------------------------
  * Surrogate network (not part of the paper): maps control-node velocities to

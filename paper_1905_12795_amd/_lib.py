@@ -65,7 +65,7 @@ SIGNATURES = {
                                            ctypes.c_size_t, _P(Tuning), _vp]),
     "empso_misfit_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int64]),
     "empso_gradient_workspace_bytes": (ctypes.c_size_t, [_vp, ctypes.c_int32]),
-    "empso_gradient": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, ctypes.c_int32, _vp, ctypes.c_size_t, _vp]),
+    "empso_gradient": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_int32, _vp, ctypes.c_size_t, _vp]),
     "empso_misfit": (ctypes.c_int, [_vp, _vp, ctypes.c_int64, _vp, _vp, ctypes.c_size_t, _vp]),
     "empso_fitness_workspace_bytes": (ctypes.c_size_t, [_P(_vp), ctypes.c_int32, _P(ctypes.c_int32),
                                                         ctypes.c_int32]),

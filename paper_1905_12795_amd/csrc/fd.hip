@@ -1477,15 +1477,16 @@ struct GradShared {
 };
 
 // Field slots of a run: 0 .. K+1 segment levels (the forward pass uses 0..2
-// as a ring), K+2 .. K+4 adjoint ring, K+5 gradient accumulator, then two per
-// checkpoint.
+// as a ring), K+2 .. K+4 adjoint ring, K+5 gradient accumulator, K+6
+// illumination accumulator, then two per checkpoint.
 struct GradSlots {
     int K, ncheck;
     int seg(int i) const { return i; }
     int adj(int k) const { return K + 2 + ((k % 3) + 3) % 3; }
     int gacc() const { return K + 5; }
-    int ck(int j, int which) const { return K + 6 + 2 * j + which; }
-    int total() const { return K + 6 + 2 * ncheck; }
+    int illum() const { return K + 6; }
+    int ck(int j, int which) const { return K + 7 + 2 * j + which; }
+    int total() const { return K + 7 + 2 * ncheck; }
 };
 
 static int grad_interval(const empso_problem *p, int K) {
@@ -1576,6 +1577,8 @@ __global__ __launch_bounds__(256) void k_gstep(const GradRun *__restrict__ runs,
             const float u0 = (&Uk4.x)[q], u1 = (&Uk14.x)[q], u2 = (&Uk24.x)[q];
             float *g = R.fields + (size_t)gacc * sh.gfs + o + q;
             *g = fmaf(un, (1.0f + a) * (u0 - u1) - (1.0f - a) * (u1 - u2), *g);
+            float *il = R.fields + (size_t)(gacc + 1) * sh.gfs + o + q;      // illumination: sum of u^k^2
+            *il = fmaf(u0, u0, *il);
         }
     }
 }
@@ -1592,20 +1595,25 @@ __global__ void k_gcopy(const GradRun *__restrict__ runs, size_t gfs, int src, i
 // it (its own, plus the absorbing-layer strip or corner beyond an edge), over
 // all runs in a fixed order, times 2 / (v^3 dt^2).
 __global__ void k_gfold(const GradRun *__restrict__ runs, int nruns, const GradShared sh, int gacc, const float *vp,
-                        int nz, int nx, int nbl, double dt, float *grad) {
+                        int nz, int nx, int nbl, double dt, float *grad, float *illum) {
     const int64_t n = (int64_t)nz * nx;
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
         const int i = (int)(q / nx), j = (int)(q - (int64_t)i * nx);
         const int I0 = i == 0 ? 0 : i + nbl, I1 = i == nz - 1 ? sh.Nz - 1 : i + nbl;
         const int J0 = j == 0 ? 0 : j + nbl, J1 = j == nx - 1 ? sh.Nx - 1 : j + nbl;
-        double sum = 0.0;
+        double sum = 0.0, ill = 0.0;
         for (int r = 0; r < nruns; ++r) {
             const float *g = runs[r].fields + (size_t)gacc * sh.gfs;
+            const float *h = g + sh.gfs;
             for (int I = I0; I <= I1; ++I)
-                for (int J = J0; J <= J1; ++J) sum += (double)g[(size_t)(I + kRing) * sh.S + J + kRing];
+                for (int J = J0; J <= J1; ++J) {
+                    sum += (double)g[(size_t)(I + kRing) * sh.S + J + kRing];
+                    ill += (double)h[(size_t)(I + kRing) * sh.S + J + kRing];
+                }
         }
         const double v = vp[q];
         grad[q] = (float)(sum * 2.0 / (v * v * v * dt * dt));
+        if (illum) illum[q] = (float)ill;
     }
 }
 
@@ -1657,7 +1665,7 @@ extern "C" size_t empso_gradient_workspace_bytes(const empso_problem *p, int32_t
 }
 
 extern "C" int empso_gradient(const empso_problem *p, const float *vp_d, const float *obs_d, float *grad_d,
-                              float *misfit_d, int32_t checkpoint_every, void *ws, size_t ws_bytes,
+                              float *misfit_d, float *illum_d, int32_t checkpoint_every, void *ws, size_t ws_bytes,
                               empso_stream stream) {
     clear_error();
     if (!p || !vp_d || !obs_d || !grad_d || !misfit_d || !ws) EMPSO_FAIL(EMPSO_EINVAL, "NULL argument");
@@ -1760,7 +1768,7 @@ extern "C" int empso_gradient(const empso_problem *p, const float *vp_d, const f
     }
     const int64_t npts = (int64_t)p->g.nz * p->g.nx;
     k_gfold<<<(int)std::min<int64_t>(2048, (npts + 255) / 256), 256, 0, st>>>(runs, ns, sh, sl.gacc(), vp_d, p->g.nz,
-                                                                              p->g.nx, p->g.nbl, p->g.dt, grad_d);
+                                                                              p->g.nx, p->g.nbl, p->g.dt, grad_d, illum_d);
     k_gmisfit<<<1, 256, 0, st>>>(runs, ns, p->g.nrec, misfit_d);
     EMPSO_HIP(hipGetLastError());
     return EMPSO_OK;

@@ -157,10 +157,11 @@ def forward_shots(prob, vp, shot0=0, nsh=None, out=None, ws=None, tuning=None):
     return out
 
 
-def gradient(prob, vp, obs, checkpoint_every=0, ws=None):
+def gradient(prob, vp, obs, checkpoint_every=0, ws=None, illumination=False):
     """Misfit over all shots and its gradient with respect to the physical
     model (discrete adjoint with checkpoints, library call). vp[nz][nx] and
-    obs[nshots][nt][nrec] are device FP32. Returns (misfit [1], grad [nz][nx])."""
+    obs[nshots][nt][nrec] are device FP32. Returns (misfit [1], grad [nz][nx]),
+    plus the source illumination [nz][nx] when illumination=True."""
     _need(vp, torch.float32, (prob.info.nz, prob.info.nx), "vp")
     _need(obs, torch.float32, (prob.nshots, prob.nt, prob.nrec), "obs")
     need = lib.empso_gradient_workspace_bytes(prob.handle, int(checkpoint_every))
@@ -170,9 +171,10 @@ def gradient(prob, vp, obs, checkpoint_every=0, ws=None):
         ws = workspace(need, vp.device)
     grad = torch.empty_like(vp)
     mis = torch.empty(1, dtype=torch.float32, device=vp.device)
-    check(lib.empso_gradient(prob.handle, _ptr(vp), _ptr(obs), _ptr(grad), _ptr(mis), int(checkpoint_every),
-                             _ptr(ws), ws.numel(), _stream()))
-    return mis, grad
+    ill = torch.empty_like(vp) if illumination else None
+    check(lib.empso_gradient(prob.handle, _ptr(vp), _ptr(obs), _ptr(grad), _ptr(mis), _ptr(ill),
+                             int(checkpoint_every), _ptr(ws), ws.numel(), _stream()))
+    return (mis, grad, ill) if illumination else (mis, grad)
 
 
 def misfit(a, b, out=None, ws=None):

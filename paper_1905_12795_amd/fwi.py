@@ -25,12 +25,15 @@ def model_misfit(prob, vp, obs):
 
 
 def invert(prob, obs, vp0, iterations, vmin=None, vmax=None, first_step=20.0, armijo=1e-4, max_trials=8,
-           checkpoint_every=0, log=None):
+           checkpoint_every=0, precondition=True, eps=1e-3, log=None):
     """Steepest descent with Barzilai-Borwein steps and backtracking.
 
     vp0: host or device [nz][nx] starting model. first_step: the first trial
-    step moves the model by at most this many m/s. Returns (vp host FP64,
-    history of per-iteration records: misfit, step, trials, gradient time).
+    step moves the model by at most this many m/s. precondition: scale the
+    gradient by 1/(illumination + eps * max illumination), the source
+    illumination of the starting model (a fixed diagonal metric, so the BB
+    steps stay consistent). Returns (vp host FP64, history of per-iteration
+    records: misfit, step, trials, gradient time).
     """
     vmin = float(prob.vmin if vmin is None else vmin)
     vmax = float(prob.vmax if vmax is None else vmax)
@@ -38,27 +41,36 @@ def invert(prob, obs, vp0, iterations, vmin=None, vmax=None, first_step=20.0, ar
     v = np.clip(np.asarray(torch.as_tensor(vp0).cpu(), dtype=np.float64), vmin, vmax)
     ws = fd.workspace(fd.lib.empso_gradient_workspace_bytes(prob.handle, int(checkpoint_every)), dev)
 
+    P = None
+
     def grad_at(x):
+        nonlocal P
         t0 = time.perf_counter()
-        m, g = fd.gradient(prob, torch.tensor(x, dtype=torch.float32, device=dev), obs, checkpoint_every, ws)
-        gh = g.cpu().numpy().astype(np.float64)
-        return float(m), gh, time.perf_counter() - t0
+        out = fd.gradient(prob, torch.tensor(x, dtype=torch.float32, device=dev), obs, checkpoint_every, ws,
+                          illumination=precondition and P is None)
+        gh = out[1].cpu().numpy().astype(np.float64)
+        if precondition and P is None:
+            ill = out[2].cpu().numpy().astype(np.float64)
+            P = 1.0 / (ill + eps * ill.max())
+        return float(out[0]), gh, time.perf_counter() - t0
 
     J, g, tg = grad_at(v)
+    if P is None:
+        P = np.ones_like(g)
     hist = [{"iteration": 0, "misfit": J, "gradient_s": tg}]
-    alpha = first_step / max(np.abs(g).max(), 1e-300)
+    alpha = first_step / max(np.abs(P * g).max(), 1e-300)
     v_prev = g_prev = None
     for it in range(1, iterations + 1):
         if v_prev is not None:
             s = v - v_prev
-            y = g - g_prev
+            y = P * (g - g_prev)
             sy = float(np.sum(s * y))
             if sy > 0:
-                alpha = float(np.sum(s * s)) / sy                 # BB1
+                alpha = float(np.sum(s * s)) / sy                 # BB1 in the metric of P
         trials = 0
         while True:
             trials += 1
-            v_new = np.clip(v - alpha * g, vmin, vmax)
+            v_new = np.clip(v - alpha * P * g, vmin, vmax)
             J_new = model_misfit(prob, torch.tensor(v_new, dtype=torch.float32, device=dev), obs)
             if J_new <= J - armijo * float(np.sum(g * (v - v_new))) or trials >= max_trials:
                 break

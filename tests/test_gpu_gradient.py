@@ -152,3 +152,21 @@ def test_local_fwi_reduces_misfit_and_model_error(gfd):
     assert all(b <= a for a, b in zip(J, J[1:]))
     assert J[-1] < 0.5 * J[0]
     assert fwi.rms_error(v, truth) < fwi.rms_error(vp, truth)
+
+
+def test_illumination_equals_trace_energy_on_an_interior_receiver_row(gfd):
+    """With receivers on an interior row, the illumination there is the sum
+    over shots and samples n >= 1 of the squared oracle traces."""
+    g = _tiny()
+    g["rec"] = [[50.0, 10.0 * j] for j in range(3, 28, 3)]
+    op = ofd.Problem(g)
+    gp = gfd.Problem(g, dt=op.dt, nt=op.nt)
+    vp, _ = _models(op.nz, op.nx, op.dz, op.dx)
+    vp = vp.astype(np.float32).astype(np.float64)
+    to = ofd.forward_shots(op, vp)
+    want = np.sum(to[:, 1:, :] ** 2, axis=(0, 1))
+    obs = torch.zeros((op.nshots, op.nt, op.nrec), dtype=torch.float32, device="cuda")
+    _, _, ill = gfd.gradient(gp, torch.tensor(vp, dtype=torch.float32, device="cuda"), obs, illumination=True)
+    got = ill.cpu().numpy()[5, 3:28:3].astype(np.float64)
+    assert np.allclose(got, want, rtol=1e-4, atol=0), (got, want)
+    assert float(ill.min()) >= 0.0

@@ -125,4 +125,4 @@ def test_empty_batch_is_a_no_op(L):
 
 def test_gradient_null_arguments(L):
     assert L.lib.empso_gradient_workspace_bytes(None, 0) == 0
-    assert L.lib.empso_gradient(None, None, None, None, None, 0, None, 0, None) == -1
+    assert L.lib.empso_gradient(None, None, None, None, None, None, 0, None, 0, None) == -1
