@@ -27,7 +27,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 # Algorithmic HBM bytes per grid-point update of the scheme: read u^n and
-# delta^n, write u^{n+1} and delta^{n+1} (FP32). The coefficient field is
+# u^{n-1}, write u^{n+1} and u^n (FP32). The coefficient field is
 # shared by the 16 shots of a particle and excluded. A launch that advances T
 # time steps performs T updates per point.
 BYTES_PER_UPDATE = 16
@@ -35,10 +35,16 @@ METRIC = "fitness evals/s and Gpt-updates/s on 1 MI355X; % HBM peak; surrogate v
 
 
 def kernel_source_hash():
-    h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_1905_12795_amd", "csrc", "fd.hip"), "rb") as f:
-        h.update(f.read())
-    return h.hexdigest()[:16]
+    """Hash of the stencil kernel's source text: the RunDesc descriptor it
+    reads plus everything from its memory-access helpers to the end of the
+    k_tb template. Edits to the file's other kernels and entry points leave
+    the committed counter measurements valid."""
+    src = open(os.path.join(ROOT, "paper_1905_12795_amd", "csrc", "fd.hip"), "rb").read()
+    a = src.index(b"struct RunDesc {")
+    a2 = src.index(b"};", a) + 2
+    b = src.index(b"// Scalar and vector accesses through explicit address spaces")
+    c = src.index(b"// Sample u^n (held in buffer `par`)")
+    return hashlib.sha256(src[a:a2] + src[b:c]).hexdigest()[:16]
 
 
 def measured_traffic(per_launch_updates, tu):
