@@ -18,7 +18,8 @@ def _stream():
 
 
 def _ptr(t):
-    return ctypes.c_void_p(t.data_ptr())
+    """Device address of a tensor (NULL for None: an optional output)."""
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
 
 
 def _need(t, dtype, shape=None, name="tensor"):
