@@ -1504,7 +1504,7 @@ static int grad_interval(const empso_problem *p, int K) {
 template <bool ADJ, bool ISO>
 __global__ __launch_bounds__(256) void k_gstep(const GradRun *__restrict__ runs, const GradShared sh, int cur,
                                                int prev, int out, float fsrc, int k, int uk, int uk1, int uk2,
-                                               int gacc) {
+                                               int gacc, int illum) {
     const int I = blockIdx.y * 4 + (int)threadIdx.y;
     const int J0 = 4 * (blockIdx.x * 64 + (int)threadIdx.x);
     if (I >= sh.Nz || J0 >= sh.Nx) return;
@@ -1577,8 +1577,10 @@ __global__ __launch_bounds__(256) void k_gstep(const GradRun *__restrict__ runs,
             const float u0 = (&Uk4.x)[q], u1 = (&Uk14.x)[q], u2 = (&Uk24.x)[q];
             float *g = R.fields + (size_t)gacc * sh.gfs + o + q;
             *g = fmaf(un, (1.0f + a) * (u0 - u1) - (1.0f - a) * (u1 - u2), *g);
-            float *il = R.fields + (size_t)(gacc + 1) * sh.gfs + o + q;      // illumination: sum of u^k^2
-            *il = fmaf(u0, u0, *il);
+            if (illum) {
+                float *il = R.fields + (size_t)(gacc + 1) * sh.gfs + o + q;  // illumination: sum of u^k^2
+                *il = fmaf(u0, u0, *il);
+            }
         }
     }
 }
@@ -1608,7 +1610,7 @@ __global__ void k_gfold(const GradRun *__restrict__ runs, int nruns, const GradS
             for (int I = I0; I <= I1; ++I)
                 for (int J = J0; J <= J1; ++J) {
                     sum += (double)g[(size_t)(I + kRing) * sh.S + J + kRing];
-                    ill += (double)h[(size_t)(I + kRing) * sh.S + J + kRing];
+                    if (illum) ill += (double)h[(size_t)(I + kRing) * sh.S + J + kRing];
                 }
         }
         const double v = vp[q];
@@ -1727,15 +1729,17 @@ extern "C" int empso_gradient(const empso_problem *p, const float *vp_d, const f
     auto step_fwd = [&](int n, int cur, int prev, int out) {
         const float fs = wav[n] * p->wscale;
         if (iso)
-            k_gstep<false, true><<<grd, blk, 0, st>>>(runs, sh, cur, prev, out, fs, n, 0, 0, 0, 0);
+            k_gstep<false, true><<<grd, blk, 0, st>>>(runs, sh, cur, prev, out, fs, n, 0, 0, 0, 0, 0);
         else
-            k_gstep<false, false><<<grd, blk, 0, st>>>(runs, sh, cur, prev, out, fs, n, 0, 0, 0, 0);
+            k_gstep<false, false><<<grd, blk, 0, st>>>(runs, sh, cur, prev, out, fs, n, 0, 0, 0, 0, 0);
     };
     auto step_adj = [&](int k, int cur, int prev, int out, int uk, int uk1, int uk2) {
         if (iso)
-            k_gstep<true, true><<<grd, blk, 0, st>>>(runs, sh, cur, prev, out, 0.0f, k, uk, uk1, uk2, sl.gacc());
+            k_gstep<true, true><<<grd, blk, 0, st>>>(runs, sh, cur, prev, out, 0.0f, k, uk, uk1, uk2, sl.gacc(),
+                                                     illum_d != nullptr);
         else
-            k_gstep<true, false><<<grd, blk, 0, st>>>(runs, sh, cur, prev, out, 0.0f, k, uk, uk1, uk2, sl.gacc());
+            k_gstep<true, false><<<grd, blk, 0, st>>>(runs, sh, cur, prev, out, 0.0f, k, uk, uk1, uk2, sl.gacc(),
+                                                      illum_d != nullptr);
     };
     auto copy = [&](int src, int dst) { k_gcopy<<<dim3(cblocks, ns), 256, 0, st>>>(runs, gfs, src, dst); };
 

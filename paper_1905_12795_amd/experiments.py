@@ -132,6 +132,54 @@ def local_fwi(workload, search_iters, fwi_iters, seed):
            "rms_error_empso": fwi.rms_error(v0.cpu().numpy(), truth), "rms_error_fwi": fwi.rms_error(v, truth)})
 
 
+def gradient_timing(workload, reps, modes=(False, True)):
+    """Misfit gradients of a linear 1500-5500 m/s model over all shots of a
+    workload (one untimed, `reps` timed), with and without the illumination."""
+    g = config(workload)
+    prob = fd.Problem(g)
+    dobs = search.observed_for(g, prob, true_model(g))
+    nz, nx = g["nz"], g["nx"]
+    z = np.arange(nz, dtype=np.float64)[:, None] / (nz - 1)
+    v0 = torch.tensor(np.repeat(1500.0 + 4000.0 * z, nx, axis=1), dtype=torch.float32, device="cuda")
+    ws = fd.workspace(fd.lib.empso_gradient_workspace_bytes(prob.handle, 0))
+    for illum in modes:
+        fd.gradient(prob, v0, dobs, 0, ws, illumination=illum)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            out = fd.gradient(prob, v0, dobs, 0, ws, illumination=illum)
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / reps
+        _emit({"workload": workload, "illumination": illum, "seconds_per_gradient": sec,
+               "gpt_updates_per_s_three_passes": 3 * prob.updates_per_run * prob.nshots / sec / 1e9,
+               "misfit": float(out[0])})
+
+
+def mlp_timing(reps):
+    """Surrogate network at the surrogate workload's shape (D = 60, H = 256):
+    inference on 1024 candidates and training steps of 256 rows."""
+    from paper_1905_12795_amd.surrogate import Surrogate
+    gs = config("surrogate")
+    sur = Surrogate(gs["node_lo"], gs["node_hi"], seed=0)
+    X = uniform_particles(2048, gs["node_lo"], gs["node_hi"], 0)
+    sur.add(X, np.exp(np.random.default_rng(0).normal(5, 1, 2048)))
+    Xc = torch.tensor(uniform_particles(1024, gs["node_lo"], gs["node_hi"], 1), dtype=torch.float32, device="cuda")
+    idx = torch.arange(256, dtype=torch.int32, device="cuda")
+    sur.net.predict(Xc)
+    sur.net.train_step(sur.X, sur.f, idx, sur.mu, sur.sigma, 1e-4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        sur.net.predict(Xc)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(reps):
+        sur.net.train_step(sur.X, sur.f, idx, sur.mu, sur.sigma, 1e-4)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    _emit({"predict_1024_ms": (t1 - t0) / reps * 1e3, "train_step_256_ms": (t2 - t1) / reps * 1e3, "reps": reps})
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -151,9 +199,19 @@ def main():
     f.add_argument("--search-iters", type=int, default=15)
     f.add_argument("--fwi-iters", type=int, default=10)
     f.add_argument("--seed", type=int, default=1)
+    gr = sub.add_parser("gradient")
+    gr.add_argument("--workload", default="realistic", choices=["tiny", "realistic", "irregular", "crime_free", "full"])
+    gr.add_argument("--reps", type=int, default=2)
+    gr.add_argument("--plain-only", action="store_true", help="skip the run that also returns the illumination")
+    ml = sub.add_parser("mlp")
+    ml.add_argument("--reps", type=int, default=50)
     a = ap.parse_args()
     if a.cmd == "throughput":
         throughput(a.workload, a.particles, a.calls)
+    elif a.cmd == "gradient":
+        gradient_timing(a.workload, a.reps, (False,) if a.plain_only else (False, True))
+    elif a.cmd == "mlp":
+        mlp_timing(a.reps)
     elif a.cmd == "fwi":
         local_fwi(a.workload, a.search_iters, a.fwi_iters, a.seed)
     else:
