@@ -32,6 +32,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <atomic>
 #include <mutex>
 #include <type_traits>
 #include <unordered_map>
@@ -76,6 +77,7 @@ using namespace empso;
 // Problem
 // ---------------------------------------------------------------------------
 struct empso_problem {
+    uint64_t uid = 0;          // serial number: never reused, unlike the address
     empso_geometry g;
     int Nz, Nx, S;             // padded sizes, stored row stride (floats)
     int D;                     // node values per particle
@@ -199,7 +201,9 @@ extern "C" int empso_problem_create(const empso_geometry *gp, empso_problem **ou
         EMPSO_FAIL(EMPSO_ECFL, "dt = %g exceeds the stability limit %g at vmax = %g", g.dt,
                    stable_dt_raw(g.vmax, g.dz, g.dx), g.vmax);
 
+    static std::atomic<uint64_t> next_uid{1};
     empso_problem *p = new empso_problem();
+    p->uid = next_uid.fetch_add(1);
     p->g = g;
     p->g.src_zx = nullptr;
     p->g.rec_zx = nullptr;
@@ -359,7 +363,13 @@ extern "C" int empso_problem_create(const empso_geometry *gp, empso_problem **ou
     return EMPSO_OK;
 }
 
-extern "C" void empso_problem_destroy(empso_problem *p) { free_problem(p); }
+static void drop_plans_of(uint64_t uid);
+
+extern "C" void empso_problem_destroy(empso_problem *p) {
+    if (!p) return;
+    drop_plans_of(p->uid);          // cached fitness plans read this problem's tables
+    free_problem(p);
+}
 
 extern "C" int empso_problem_get_info(const empso_problem *p, empso_problem_info *info) {
     if (!p || !info) EMPSO_FAIL(EMPSO_EINVAL, "NULL argument");
@@ -917,6 +927,7 @@ static Layout make_layout(const std::vector<const empso_problem *> &pp, const st
 struct Plan {
     std::vector<const void *> key_ptrs;
     std::vector<int> key_ints;
+    std::vector<uint64_t> uids;            // problems the plan was built for
     Layout L;
     std::vector<unsigned char> host_hdr;   // host copy of the descriptor header
     unsigned char *pinned = nullptr;       // pinned staging buffer (hdr_bytes)
@@ -924,13 +935,28 @@ struct Plan {
     bool upload_pending = false;
     hipGraphExec_t exec = nullptr;
     hipStream_t cap_stream = nullptr;
-    ~Plan() {
+    // release the graph and staging (callers make sure nothing is queued)
+    void release() {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
         if (upload_done) (void)hipEventDestroy(upload_done);
         if (pinned) (void)hipHostFree(pinned);
+        exec = nullptr;
+        cap_stream = nullptr;
+        upload_done = nullptr;
+        pinned = nullptr;
+        upload_pending = false;
     }
+    ~Plan() { release(); }
 };
+
+static bool same_layout(const Layout &a, const Layout &b) {
+    return a.runs_off == b.runs_off && a.tiles_off == b.tiles_off && a.tiles1_off == b.tiles1_off &&
+           a.prun_off == b.prun_off && a.coef_off == b.coef_off && a.nodes_off == b.nodes_off &&
+           a.state_off == b.state_off && a.acc_off == b.acc_off && a.total == b.total && a.hdr_bytes == b.hdr_bytes &&
+           a.C_of_particle == b.C_of_particle && a.field_of_run == b.field_of_run && a.acc_of_run == b.acc_of_run &&
+           a.ntiles == b.ntiles && a.ntiles1 == b.ntiles1 && a.iso == b.iso;
+}
 
 static std::mutex g_plan_mu;
 static std::vector<Plan *> g_plans;   // small LRU
@@ -1128,6 +1154,28 @@ static Plan *find_or_make_plan(const std::vector<const void *> &kp, const std::v
     return p;
 }
 
+}  // namespace
+
+static void drop_plans_of(uint64_t uid) {
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    bool synced = false;
+    for (size_t i = 0; i < g_plans.size();) {
+        Plan *pl = g_plans[i];
+        if (std::find(pl->uids.begin(), pl->uids.end(), uid) != pl->uids.end()) {
+            if (!synced) {
+                (void)hipDeviceSynchronize();     // nothing of the plan may still be queued
+                synced = true;
+            }
+            delete pl;
+            g_plans.erase(g_plans.begin() + i);
+        } else {
+            ++i;
+        }
+    }
+}
+
+namespace {
+
 static bool valid_tuning(const empso_tuning &t) {
     return (t.bz == 20 || t.bz == 40 || t.bz == 80 || t.bz == 160) && t.tsteps >= 1 && t.tsteps <= kMaxT && t.prefetch == 1 &&
            (t.use_graph == 0 || t.use_graph == 1);
@@ -1292,11 +1340,18 @@ extern "C" int empso_fitness_batch(const empso_problem *const *probs, int32_t np
     const size_t need = make_layout(pp, runs, Dmax, kMinBz, kMaxT).total;
     if (ws_bytes < need) EMPSO_FAIL(EMPSO_EWORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
 
+    // plan key: buffers, problems by serial number (a destroyed problem's
+    // address can come back for a new one), batch composition and tuning
     std::vector<const void *> kp;
     std::vector<int> ki;
+    std::vector<uint64_t> uids;
     kp.push_back(ws);
     kp.push_back(fitness_d);
-    for (int q = 0; q < nprob; ++q) kp.push_back(probs[q]);
+    for (int q = 0; q < nprob; ++q) {
+        uids.push_back(probs[q]->uid);
+        ki.push_back((int)(probs[q]->uid & 0x7fffffff));
+        ki.push_back((int)(probs[q]->uid >> 31));
+    }
     ki.push_back(np);
     ki.push_back(tu.bz);
     ki.push_back(tu.tsteps);
@@ -1307,7 +1362,17 @@ extern "C" int empso_fitness_batch(const empso_problem *const *probs, int32_t np
     std::lock_guard<std::mutex> lk(g_plan_mu);
     bool fresh;
     Plan *pl = find_or_make_plan(kp, ki, &fresh);
-    if (fresh) pl->L = make_layout(pp, runs, Dmax, tu.bz, tu.tsteps);
+    Layout Lnow = make_layout(pp, runs, Dmax, tu.bz, tu.tsteps);
+    if (!fresh && !same_layout(pl->L, Lnow)) {
+        // never replay a plan built for another layout: rebuild it
+        (void)hipDeviceSynchronize();
+        pl->release();
+        fresh = true;
+    }
+    if (fresh) {
+        pl->L = std::move(Lnow);
+        pl->uids = uids;
+    }
     unsigned char *w = reinterpret_cast<unsigned char *>(ws);
     build_header(*pl, w, pp, runs, std::vector<const float *>(), nodes_h, ld_nodes, Dmax, tu);
     return run_plan(pl, w, (int)runs.size(), np, pp[0]->g.nt, tu, fitness_d, (hipStream_t)stream);

@@ -371,3 +371,29 @@ def test_irregular_workload_vp_matches_oracle(gfd):
     for k in range(2):
         vo = op.model(X[k].astype(np.float32).astype(np.float64))
         assert np.max(np.abs(vg[k] - vo) / vo) < 2e-6, k
+
+
+def test_new_problem_after_a_destroyed_one_gets_a_fresh_plan(gfd):
+    """Fitness plans are cached per (buffers, problems, batch, tuning). A
+    problem created after another was destroyed may land at the same address
+    and the caching allocator hands out the same buffers; the new problem
+    (here with more node values) must still get its own plan."""
+    import gc
+    g1 = _small_geom()
+    op1, gp1 = _pair(gfd, g1)
+    rng = np.random.default_rng(21)
+    d1 = torch.tensor(rng.standard_normal((3, gp1.nt, gp1.nrec)).astype(np.float32) * 1e-3, device="cuda")
+    fb1 = gfd.FitnessBatch([gp1], [d1], [0] * 4)
+    fb1(rng.uniform(1400, 2700, (4, 12)))
+    del fb1, gp1
+    gc.collect()
+    g2 = _layered_small_geom()                      # same grid, 14 node values instead of 12
+    op2, gp2 = _pair(gfd, g2)
+    to = ofd.forward_shots(op2, op2.model(np.full(14, 2000.0)))
+    dobs = to.astype(np.float32)
+    X = rng.uniform(1400, 2700, (4, 14))
+    fo, _ = ofd.fitness_batch(op2, X.astype(np.float32).astype(np.float64), dobs)
+    fg = gfd.FitnessBatch([gp2], [torch.tensor(dobs, device="cuda")], [0] * 4)(X).cpu().numpy()
+    n2 = float(np.sum(dobs.astype(np.float64) ** 2))
+    for k in range(4):
+        assert _fit_close(float(fg[k]), fo[k], n2), (k, fg[k], fo[k])
