@@ -76,7 +76,7 @@ def throughput(workload, particles, calls):
            "grids": [[p.info.Nz, p.info.Nx] for p in probs], "nt": probs[0].nt})
 
 
-def surrogate(workload, iters, seeds, K, log):
+def surrogate(workload, iters, seeds, K, log, members=1, kappa=0.0):
     g = config(workload)
     if workload in ("realistic", "irregular", "crime_free"):
         g = dict(g)
@@ -91,7 +91,8 @@ def surrogate(workload, iters, seeds, K, log):
         target = 1.01 * hp[-1]["best"]
         res.update(plain_final=hp[-1]["best"], plain_evals=hp[-1]["evaluations"], plain_wall=hp[-1]["wall_s"])
         for mode in ("screened", "random"):
-            h = search.run(g, dobs, prob, iters, mode, seed=seed, K=K, log_path=log)
+            h = search.run(g, dobs, prob, iters, mode, seed=seed, K=K, log_path=log,
+                           sur_kw={"members": members, "kappa": kappa} if mode == "screened" else None)
             hist[mode].append(h)
             e, t = search.evals_to_reach(h, target)
             res.update({mode + "_final": h[-1]["best"], mode + "_evals_to_plain": e, mode + "_wall_to_plain": t})
@@ -194,6 +195,8 @@ def main():
     s.add_argument("--seeds", default="1,2,3")
     s.add_argument("--K", type=int, default=16)
     s.add_argument("--log", default=None)
+    s.add_argument("--members", type=int, default=1, help="networks in the surrogate ensemble")
+    s.add_argument("--kappa", type=float, default=0.0, help="score = members' mean + kappa * spread")
     f = sub.add_parser("fwi")
     f.add_argument("--workload", default="realistic", choices=["realistic", "irregular", "crime_free"])
     f.add_argument("--search-iters", type=int, default=15)
@@ -215,7 +218,7 @@ def main():
     elif a.cmd == "fwi":
         local_fwi(a.workload, a.search_iters, a.fwi_iters, a.seed)
     else:
-        surrogate(a.workload, a.iters, [int(x) for x in a.seeds.split(",")], a.K, a.log)
+        surrogate(a.workload, a.iters, [int(x) for x in a.seeds.split(",")], a.K, a.log, a.members, a.kappa)
 
 
 if __name__ == "__main__":

@@ -110,12 +110,23 @@ class MLP:
 
 
 class Surrogate:
-    """MLP plus the on-device dataset of (nodes, FD fitness) pairs it learns from."""
+    """MLP (or a small ensemble of them) plus the on-device dataset of
+    (nodes, FD fitness) pairs it learns from.
+
+    members > 1: independently initialised networks trained on independent
+    mini-batches of the same data, each with steps_per_update / members Adam
+    steps per update (the same cost as one network); a candidate is scored
+    by the members' mean plus kappa times their spread, so candidates the
+    members disagree on (typically far from any evaluated particle) rank
+    worse.
+    """
 
     def __init__(self, lo, hi, H=256, seed=0, lr=1e-3, batch=256, steps_per_update=64, capacity=65536,
-                 device="cuda"):
-        self.net = MLP(lo, hi, H=H, seed=seed, device=device)
+                 members=1, kappa=0.0, device="cuda"):
+        self.nets = [MLP(lo, hi, H=H, seed=seed + 1000 * m, device=device) for m in range(int(members))]
+        self.net = self.nets[0]
         self.D = self.net.D
+        self.kappa = float(kappa)
         self.lr, self.batch, self.steps_per_update = float(lr), int(batch), int(steps_per_update)
         self.X = torch.empty((capacity, self.D), dtype=torch.float32, device=device)
         self.f = torch.empty(capacity, dtype=torch.float32, device=device)
@@ -140,23 +151,31 @@ class Surrogate:
         self.sigma = float(max(lf.std(), 1e-6))
 
     def train(self, steps=None):
-        """Adam steps on random mini-batches of the dataset; returns the last loss."""
+        """Adam steps on random mini-batches of the dataset (split over the
+        members); returns the last loss."""
         steps = self.steps_per_update if steps is None else steps
+        per = max(1, steps // len(self.nets))
         if steps <= 0 or self.count == 0:
             return None
         # every step's mini-batch indices in one upload: a host-to-device copy
         # per step would wait for the previous step's kernels each time
         b = min(self.batch, self.count)
-        idx = torch.as_tensor(self.rng.integers(0, self.count, (steps, b)).astype(np.int32), device=self.X.device)
+        idx = torch.as_tensor(self.rng.integers(0, self.count, (len(self.nets) * per, b)).astype(np.int32),
+                              device=self.X.device)
         loss = None
-        for k in range(steps):
-            loss = self.net.train_step(self.X, self.f, idx[k], self.mu, self.sigma, self.lr)
+        for m, net in enumerate(self.nets):
+            for k in range(per):
+                loss = net.train_step(self.X, self.f, idx[m * per + k], self.mu, self.sigma, self.lr)
         return float(loss.item())
 
     def predict(self, X):
-        """Host [n][D] -> host predicted standardised log-misfit [n]."""
+        """Host [n][D] -> host score [n]: the predicted standardised log-misfit
+        (members' mean + kappa * spread for an ensemble)."""
         Xd = torch.as_tensor(np.asarray(X, np.float32), device=self.X.device)
-        return self.net.predict(Xd).cpu().numpy().astype(np.float64)
+        if len(self.nets) == 1:
+            return self.net.predict(Xd).cpu().numpy().astype(np.float64)
+        P = np.stack([n.predict(Xd).cpu().numpy().astype(np.float64) for n in self.nets])
+        return P.mean(axis=0) + self.kappa * P.std(axis=0)
 
 
 class RandomRanker:
