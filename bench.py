@@ -278,7 +278,7 @@ def main():
         "gpt_updates_per_s": gpt,
         "fitness_call_ms": float(np.mean(gpu_ms)),
         "best_fitness": float(swarm.fg),
-        "roofline": {"bound": "hbm", "kernel": "k_tb<%d,%d>" % (tu.bz // 10, T), "achieved": achieved,
+        "roofline": {"bound": "hbm", "kernel": "k_tb<%d> (tiles of about %d rows)" % (T, tu.bz), "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
                      "algorithmic_bytes_per_launch": alg, "updates_per_launch": upd_per_launch,

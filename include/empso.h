@@ -124,7 +124,9 @@ typedef struct {
  * bit-identical results; only the speed changes. */
 typedef struct {
     int32_t variant;         /* reserved, 0                                             */
-    int32_t bz;              /* output rows per tile: 20, 40, 80 or 160                  */
+    int32_t bz;              /* target output rows per tile, a multiple of 20 in 20..320;
+                              * each grid's rows are split into equal strips of about
+                              * this height (rounded up to multiples of 10)             */
     int32_t tsteps;          /* time steps per launch (temporal-blocking depth): 1..4   */
     int32_t prefetch;        /* rows of u requested ahead of use: 1                     */
     int32_t use_graph;       /* 1: replay the time loop from a captured HIP graph       */
@@ -216,8 +218,8 @@ int empso_fitness_batch(const empso_problem *const *probs, int32_t nprob,
 int empso_default_tuning(empso_tuning *out);
 
 /* Autotuner: with the same arguments as empso_fitness_batch, time a few
- * launches of the finite-difference kernel for every supported tile height
- * and temporal-blocking depth on this batch and write the fastest tuning to
+ * launches of the finite-difference kernel for every tile height of 20, 40,
+ * 80, 160, 240 and 320 rows and temporal-blocking depth on this batch and write the fastest tuning to
  * *best (graph replay on) and its time per time step in microseconds to
  * *best_us_per_step (may be NULL). Every tuning gives bit-identical results.
  * Synchronises the stream; overwrites the workspace. */

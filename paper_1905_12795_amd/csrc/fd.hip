@@ -579,7 +579,8 @@ __device__ __forceinline__ float from_lane_above(float v) {
 // A wavefront loads 256 columns (4 per lane) and owns the central 256 - 8T of
 // them: the level-t result is exact 4t columns in from either edge, so
 // neighbouring tiles overlap by 8T columns and recompute them. In z, the
-// wavefront owns M * 10 rows and marches down from 4T rows above them. In
+// wavefront owns the rows [s0, s1) its tile names and marches down from 4T
+// rows above them, in blocks of 10 steps. In
 // each step of the march, level 1 updates row r from u^n rows r-4 .. r+4 (a
 // queue of 10 slots with one row requested ahead) and u^{n-1}(r); level t
 // updates row r - 4(t-1) from the 9-row queue of level t-1's results and the
@@ -591,11 +592,10 @@ __device__ __forceinline__ float from_lane_above(float v) {
 // the incoming fields, so they stay exactly zero at every level.
 // Receiver samples of each level (u^{n+t-1} on the receiver row) are parked
 // in LDS and accumulated after the march by the owning lanes.
-template <int M, int T, bool ISO>
+template <int T, bool ISO>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(T < 3 ? 3 : 2))) void k_tb(const RunDesc *__restrict__ runs, const int4 *__restrict__ tiles,
                                             int ntiles, int n, int par) {
     constexpr int NS = kQueue;
-    constexpr int BZ = M * NS;
     constexpr int FILL = 8 * (T - 1);               // march steps before the first owned row
     constexpr int TQ = T > 1 ? T - 1 : 1;
     __shared__ float4 srec[4][T][64];
@@ -627,7 +627,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(T < 3 ? 3 :
     const int J0 = c - kRing;
     const bool own = (lane >= T) && (lane < 64 - T);
     const int s0 = t.y;
-    const int s1 = min(s0 + BZ, bot);
+    const int s1 = min(t.w, bot);                   // the tile's owned stored rows are [s0, s1)
     const int lcol = 4 * cc;                        // byte offset of the lane's columns in a row
     const int rowb = 4 * S;                         // bytes per stored row
 
@@ -962,22 +962,19 @@ static std::mutex g_plan_mu;
 static std::vector<Plan *> g_plans;   // small LRU
 static const size_t kMaxPlans = 8;
 
-static int launch_tb(int bz, int T, bool iso, const RunDesc *runs, const int4 *tiles, int ntiles, int n, int par,
+static int launch_tb(int T, bool iso, const RunDesc *runs, const int4 *tiles, int ntiles, int n, int par,
                      hipStream_t st) {
     int blocks = (ntiles + 3) / 4;
     blocks = (blocks + 7) / 8 * 8;
-#define EMPSO_TB_CASE(B, TT)                                                                 \
-    if (bz == B && T == TT) {                                                                \
-        if (iso)                                                                             \
-            k_tb<B / kQueue, TT, true><<<blocks, 256, 0, st>>>(runs, tiles, ntiles, n, par);  \
-        else                                                                                 \
-            k_tb<B / kQueue, TT, false><<<blocks, 256, 0, st>>>(runs, tiles, ntiles, n, par); \
-        return EMPSO_OK;                                                                     \
+#define EMPSO_TB_CASE(TT)                                                                 \
+    if (T == TT) {                                                                        \
+        if (iso)                                                                          \
+            k_tb<TT, true><<<blocks, 256, 0, st>>>(runs, tiles, ntiles, n, par);          \
+        else                                                                              \
+            k_tb<TT, false><<<blocks, 256, 0, st>>>(runs, tiles, ntiles, n, par);         \
+        return EMPSO_OK;                                                                  \
     }
-    EMPSO_TB_CASE(20, 1) EMPSO_TB_CASE(40, 1) EMPSO_TB_CASE(80, 1) EMPSO_TB_CASE(160, 1)
-    EMPSO_TB_CASE(20, 2) EMPSO_TB_CASE(40, 2) EMPSO_TB_CASE(80, 2) EMPSO_TB_CASE(160, 2)
-    EMPSO_TB_CASE(20, 3) EMPSO_TB_CASE(40, 3) EMPSO_TB_CASE(80, 3) EMPSO_TB_CASE(160, 3)
-    EMPSO_TB_CASE(20, 4) EMPSO_TB_CASE(40, 4) EMPSO_TB_CASE(80, 4) EMPSO_TB_CASE(160, 4)
+    EMPSO_TB_CASE(1) EMPSO_TB_CASE(2) EMPSO_TB_CASE(3) EMPSO_TB_CASE(4)
 #undef EMPSO_TB_CASE
     return EMPSO_ENOTSUP;
 }
@@ -998,10 +995,10 @@ static int enqueue_all(const Plan &pl, unsigned char *ws, int nruns, int np, int
     while (n < nt - 1) {
         int rc;
         if (n + tu.tsteps <= nt - 1) {
-            rc = launch_tb(tu.bz, tu.tsteps, L.iso, runs, tiles, L.ntiles, n, par, st);
+            rc = launch_tb(tu.tsteps, L.iso, runs, tiles, L.ntiles, n, par, st);
             n += tu.tsteps;
         } else {
-            rc = launch_tb(kTailBz, 1, L.iso, runs, tiles1, L.ntiles1, n, par, st);
+            rc = launch_tb(1, L.iso, runs, tiles1, L.ntiles1, n, par, st);
             n += 1;
         }
         if (rc) return rc;
@@ -1022,11 +1019,16 @@ static void fill_tiles(int4 *td, const std::vector<const empso_problem *> &pp, c
         const empso_problem *p = pp[q];
         size_t r1 = r0;
         while (r1 < runs.size() && runs[r1].particle == (int)q) ++r1;
-        const int zt = (p->Nz + bz - 1) / bz, xt = (p->Nx + W - 1) / W;
+        // z-strips of about bz rows, balanced over the grid (heights rounded
+        // up to the march's 10-step blocks, the last strip takes the rest)
+        const int nstrips = (p->Nz + bz - 1) / bz;
+        const int h = ((p->Nz + nstrips - 1) / nstrips + kQueue - 1) / kQueue * kQueue;
+        const int zt = (p->Nz + h - 1) / h, xt = (p->Nx + W - 1) / W;
         for (int zs = 0; zs < zt; ++zs)
             for (int xs = 0; xs < xt; ++xs)
                 for (size_t r = r0; r < r1; ++r)
-                    td[k++] = make_int4((int)r, kRing + zs * bz, kRing + xs * W - 4 * T, 0);
+                    td[k++] = make_int4((int)r, kRing + zs * h, kRing + xs * W - 4 * T,
+                                        kRing + std::min((zs + 1) * h, p->Nz));
         r0 = r1;
     }
 }
@@ -1177,7 +1179,7 @@ static void drop_plans_of(uint64_t uid) {
 namespace {
 
 static bool valid_tuning(const empso_tuning &t) {
-    return (t.bz == 20 || t.bz == 40 || t.bz == 80 || t.bz == 160) && t.tsteps >= 1 && t.tsteps <= kMaxT && t.prefetch == 1 &&
+    return t.bz >= 20 && t.bz <= 320 && t.bz % 20 == 0 && t.tsteps >= 1 && t.tsteps <= kMaxT && t.prefetch == 1 &&
            (t.use_graph == 0 || t.use_graph == 1);
 }
 
@@ -1424,10 +1426,10 @@ static int time_one(const std::vector<const empso_problem *> &pp, const std::vec
     k_zero<<<2048, 256, 0, st>>>(reinterpret_cast<float4 *>(w + L.state_off), (int64_t)(L.total - L.state_off) / 16);
     k_coef<<<dim3(512, (int)pp.size()), 256, 0, st>>>(reinterpret_cast<const CoefDesc *>(w + L.coef_off));
     for (int r = 0; r < warm; ++r)
-        if (launch_tb(tu.bz, tu.tsteps, L.iso, rd, td, L.ntiles, 0, 0, st)) EMPSO_FAIL(EMPSO_ENOTSUP, "bad tuning");
+        if (launch_tb(tu.tsteps, L.iso, rd, td, L.ntiles, 0, 0, st)) EMPSO_FAIL(EMPSO_ENOTSUP, "bad tuning");
     EMPSO_HIP(hipEventRecord(e0, st));
     for (int r = 0; r < reps; ++r)
-        if (launch_tb(tu.bz, tu.tsteps, L.iso, rd, td, L.ntiles, 0, 0, st)) EMPSO_FAIL(EMPSO_ENOTSUP, "bad tuning");
+        if (launch_tb(tu.tsteps, L.iso, rd, td, L.ntiles, 0, 0, st)) EMPSO_FAIL(EMPSO_ENOTSUP, "bad tuning");
     EMPSO_HIP(hipEventRecord(e1, st));
     EMPSO_HIP(hipEventSynchronize(e1));
     EMPSO_HIP(hipGetLastError());
@@ -1477,13 +1479,13 @@ extern "C" int empso_autotune_fitness(const empso_problem *const *probs, int32_t
     hipEvent_t e0, e1;
     EMPSO_HIP(hipEventCreate(&e0));
     EMPSO_HIP(hipEventCreate(&e1));
-    const int bzs[4] = {20, 40, 80, 160};
+    const int bzs[6] = {20, 40, 80, 160, 240, 320};
     float best_us = 1e30f;
     empso_tuning bt;
     empso_default_tuning(&bt);
     std::lock_guard<std::mutex> lk(g_plan_mu);
     for (int T = 1; T <= kMaxT && rc == EMPSO_OK; ++T) {
-        for (int bi = 0; bi < 4 && rc == EMPSO_OK; ++bi) {
+        for (int bi = 0; bi < 6 && rc == EMPSO_OK; ++bi) {
             empso_tuning tu;
             empso_default_tuning(&tu);
             tu.bz = bzs[bi];

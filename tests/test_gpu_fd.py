@@ -143,7 +143,7 @@ def test_tiling_graph_and_repeat_are_bitwise_invariant(gfd):
     X = rng.uniform(1400, 2700, (7, 12))
     fb = gfd.FitnessBatch([gp], [dobs], [0] * 7)
     outs = []
-    for bz in (20, 40, 80, 160):
+    for bz in (20, 40, 80, 160, 240, 320):
         for T in (1, 2, 3, 4):
             for graph in (0, 1):
                 tu = gfd.default_tuning()
@@ -242,7 +242,7 @@ def test_autotuner_picks_a_valid_tuning_with_identical_results(gfd):
     fb = gfd.FitnessBatch([gp], [dobs], [0] * 4)
     ref = fb(X).clone()
     best, us = fb.autotune(X)
-    assert best["bz"] in (20, 40, 80, 160) and 1 <= best["tsteps"] <= 4 and best["use_graph"] == 1
+    assert best["bz"] in (20, 40, 80, 160, 240, 320) and 1 <= best["tsteps"] <= 4 and best["use_graph"] == 1
     assert us > 0
     assert fb.time_tuning(X, fb.tuning, reps=2) > 0
     assert torch.equal(fb(X), ref)
