@@ -11,8 +11,9 @@ are inputs, so the same numbers can drive this and the product driver.
 Readings where the paper is silent or inconsistent:
   * "worst" = largest misfit (the search minimises); ties keep index order.
   * velocities are clamped to [-lambda VR, lambda VR] (pso.lambda key) and
-    positions to the search box after each move ("brought back into the search
-    space"); the velocity is kept when a position is clamped.
+    positions to the search box after each move (the paper returns
+    out-of-bounds variables to the box without saying how); the velocity is
+    kept when a position is clamped.
   * the personal best is replaced only on strict improvement; the global best
     is the lowest personal best, ties to the lowest index.
 Pinned by: chi closed forms, hand-worked special cases and invariants (tests).

@@ -9,7 +9,7 @@ EMPSO pseudo-code) sorts particles by fitness and replaces the positions of
 the NM worst by the global best, each coordinate perturbed with probability
 p_em by 0.1 * VR_d * N(0, 1); their velocities are kept. Algorithm overview
 section: velocities are limited to [-lambda VR, lambda VR]; Testing approach
-section: out-of-box variables are brought back into the search space, the
+section: variables that leave their bounds return to the box, the
 mutation starts at 10 % of the iterations, c1 = 1.2, c2 = 2.9, NM = 25 %,
 p_em = 0.3.
 
