@@ -200,7 +200,7 @@ def main():
     ap.add_argument("--tsteps", type=int, default=None, help="fix the temporal-blocking depth")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(the runs shard trivially by particle or shot; see the design notes).", file=sys.stderr)
         sys.exit(2)
 
