@@ -19,7 +19,12 @@ Conventions the paper leaves open, and the reading taken here:
   * Ricker wavelet with peak frequency f0 and delay t0 = 1/f0.
   * misfit = 1/2 sum of squared residuals (the paper's l2 norm, squared and
     halved; the search only compares misfits, so any increasing transform
-    leaves it unchanged).
+    leaves it unchanged). Optional variant (geometry key "misfit" =
+    "trace_normalised"): every trace, one receiver of one shot over time, of
+    the modelled and of the observed data is divided by its own l2 norm (a
+    zero trace stays zero) before that misfit. The paper states the plain l2
+    norm; the normalisation is the usual remedy for a source whose amplitude
+    the modelling does not know.
   * control nodes form a regular ncz x ncx grid whose corners are the corners
     of the physical grid; the padded layer copies the nearest physical value.
   * the paper's irregular node grid (Testing approach section: nodes built
@@ -375,6 +380,9 @@ class Problem:
             self.levels = (np.asarray(geom["node_z"], dtype=np.float64),
                            [int(n) for n in geom["level_nodes"]],
                            np.asarray(geom["node_x"], dtype=np.float64))
+        self.misfit = geom.get("misfit", "l2")
+        if self.misfit not in ("l2", "trace_normalised"):
+            raise ValueError("misfit must be 'l2' or 'trace_normalised'")
         self.water_rows = int(geom.get("water_rows", 0))
         self.v_water = float(geom.get("v_water", 1500.0))
         self.R = float(geom.get("damp_R", 1e-3))
@@ -458,16 +466,44 @@ def unpad_adjoint(g_pad, nbl):
     return g[:, nbl:-nbl]
 
 
+def normalised_adjoint_data(d, o):
+    """Data o' for which the l2 residual d - o' is the derivative of the
+    trace-normalised misfit with respect to the modelled traces d:
+    m = 1/2 |d/|d| - o/|o||^2 has dm/dd = (d/|d|) c / |d| - o / (|d| |o|),
+    c = d.o / (|d| |o|), so o' = d - dm/dd (per trace; zero where either
+    trace is zero: m is then constant in d, or not differentiable at d = 0)."""
+    d = np.asarray(d, dtype=np.float64)
+    o = np.asarray(o, dtype=np.float64)
+    dn = np.sqrt(np.sum(d * d, axis=0))
+    on = np.sqrt(np.sum(o * o, axis=0))
+    ok = (dn > 0) & (on > 0)
+    dns, ons = np.where(ok, dn, 1.0), np.where(ok, on, 1.0)
+    c = np.sum(d * o, axis=0) / (dns * ons)
+    grad_d = np.where(ok, d * (c / dns ** 2) - o / (dns * ons), 0.0)
+    return d - grad_d
+
+
 def gradient(prob, vp, d_obs, shots=None, threads=None):
     """Misfit summed over shots and its gradient with respect to the physical
     model vp[nz][nx] (Testing approach section: the local FWI that follows
-    the global search needs the gradient of the same l2 misfit). The exact
+    the global search needs the gradient of the same misfit). The exact
     gradient of the discrete misfit: pinned against central finite
-    differences of forward_shots / misfit."""
+    differences of forward_shots / misfit. For the trace-normalised misfit
+    the adjoint is driven by the misfit's derivative with respect to the
+    modelled traces, which needs the whole traces first (a forward pass)."""
     shots = list(range(prob.nshots)) if shots is None else list(shots)
     vel = pad_edge(vp, prob.nbl)
+    norm = prob.misfit == "trace_normalised"
+
+    def one(s):
+        if not norm:
+            return gradient_run(prob, vel, s, d_obs[s])
+        tr = prob.run(vel, s)
+        _, g = gradient_run(prob, vel, s, normalised_adjoint_data(tr, d_obs[s]))
+        return misfit_normalised(tr, d_obs[s]), g
+
     with ThreadPoolExecutor(_workers(threads)) as ex:
-        out = list(ex.map(lambda s: gradient_run(prob, vel, s, d_obs[s]), shots))
+        out = list(ex.map(one, shots))
     J = float(sum(o[0] for o in out))
     g_pad = np.sum([o[1] for o in out], axis=0)
     return J, unpad_adjoint(g_pad, prob.nbl)
@@ -495,6 +531,26 @@ def misfit(a, b):
     return 0.5 * float(np.sum(r * r))
 
 
+def normalise_traces(d):
+    """Each trace (time axis -2, receivers on axis -1) divided by its l2 norm;
+    a zero trace stays zero."""
+    d = np.asarray(d, dtype=np.float64)
+    nrm = np.sqrt(np.sum(d * d, axis=-2, keepdims=True))
+    return np.divide(d, nrm, out=np.zeros_like(d), where=nrm > 0)
+
+
+def misfit_normalised(a, b):
+    """1/2 sum over traces of |a/|a| - b/|b||^2, traces along time (axis -2)."""
+    if not np.all(np.isfinite(a)):
+        return math.inf
+    return misfit(normalise_traces(a), normalise_traces(b))
+
+
+def trace_misfit(prob, a, b):
+    """The problem's misfit between modelled traces a and observed traces b."""
+    return misfit_normalised(a, b) if prob.misfit == "trace_normalised" else misfit(a, b)
+
+
 def fitness_batch(prob, nodes, d_obs, shots=None, threads=None):
     """Fitness of each particle: sum over shots of the misfit (Results section:
     a particle's fitness needs all 50 shots). nodes[P][D] FP64 (D node values),
@@ -509,7 +565,7 @@ def fitness_batch(prob, nodes, d_obs, shots=None, threads=None):
     def one(job):
         p, k, s = job
         tr = prob.run(vels[p], s)
-        return misfit(tr, d_obs[s])
+        return trace_misfit(prob, tr, d_obs[s])
 
     with ThreadPoolExecutor(_workers(threads)) as ex:
         vals = list(ex.map(one, jobs))
