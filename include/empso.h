@@ -109,7 +109,19 @@ typedef struct {
     const double *node_x;
     int32_t water_rows;      /* physical rows 0 .. water_rows-1 hold v_water (either grid) */
     double v_water;          /* within [vmin, vmax] when water_rows > 0                  */
+    /* Misfit of empso_fitness_batch (EMPSO_MISFIT_*). The paper scores
+     * fitness with the l2 misfit (Testing approach section). The optional
+     * trace-normalised variant divides every trace (one receiver of one shot,
+     * over the nt samples) of the modelled and of the observed data by its own
+     * l2 norm before the l2 misfit (a zero trace stays zero), which removes
+     * amplitude mismatches between modelled and recorded sources: per trace
+     * 1/2 |d/|d| - o/|o||^2 = 1 - d.o / (|d| |o|) when both are non-zero,
+     * 1/2 when exactly one is zero, 0 when both are. Same validation as l2. */
+    int32_t misfit;
 } empso_geometry;
+
+#define EMPSO_MISFIT_L2 0
+#define EMPSO_MISFIT_TRACE_NORMALISED 1
 
 /* Read-only facts about a problem (for sizing caller-owned arrays). */
 typedef struct {
@@ -188,6 +200,22 @@ size_t empso_misfit_workspace_bytes(int64_t n);
 int empso_misfit(const float *a_d, const float *b_d, int64_t n, float *out_d,
                  void *ws, size_t ws_bytes, empso_stream stream);
 
+/* Workspace bytes for empso_traces_misfit over nsh shots (0 on invalid arguments). */
+size_t empso_traces_misfit_workspace_bytes(const empso_problem *prob, int32_t nsh);
+
+/* The problem's misfit (l2 or trace-normalised, empso_geometry.misfit)
+ * between modelled traces traces_d and observed traces obs_d, both device
+ * FP32 [nsh][nt][nrec] (Testing approach section: the misfit that scores a
+ * model), summed over the nsh shots: out_d[0] (device FP32). This is the
+ * misfit empso_fitness_batch and empso_gradient compute inside their time
+ * loops, for traces already recorded (a line search over physical models).
+ * Per trace, FP64 sums over time in order, then a fixed-order sum over
+ * traces: deterministic. +inf if a modelled trace is not finite.
+ * nsh = 0 gives 0. EINVAL for NULL arguments or nsh < 0; EWORKSPACE if
+ * ws_bytes is too small. */
+int empso_traces_misfit(const empso_problem *prob, const float *traces_d, const float *obs_d, int32_t nsh,
+                        float *out_d, void *ws, size_t ws_bytes, empso_stream stream);
+
 /* Workspace bytes for empso_fitness_batch over np particles; particle p uses
  * problem probs[prob_of_particle[p]] (host array). 0 for an empty batch
  * (np = 0) and on invalid arguments. */
@@ -195,7 +223,8 @@ size_t empso_fitness_workspace_bytes(const empso_problem *const *probs, int32_t 
                                      const int32_t *prob_of_particle, int32_t np);
 
 /* Fitness of np particles (Results section: a particle's fitness is the sum
- * over all shots of its problem of the l2 misfit). All shots of all particles
+ * over all shots of its problem of the l2 misfit, or of the trace-normalised
+ * misfit when the problem selects it). All shots of all particles
  * advance together, one launch per time step or per block of time steps.
  *   probs[nprob]              problems (grids may differ; all must share nt)
  *   obs_d[nprob]              per problem, device FP32 [nshots][nt][nrec]

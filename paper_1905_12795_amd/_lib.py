@@ -32,7 +32,11 @@ class Geometry(ctypes.Structure):
                 ("vmin", ctypes.c_double), ("vmax", ctypes.c_double), ("damp_R", ctypes.c_double),
                 ("node_z", ctypes.POINTER(ctypes.c_double)), ("level_nodes", ctypes.POINTER(ctypes.c_int32)),
                 ("node_x", ctypes.POINTER(ctypes.c_double)), ("water_rows", ctypes.c_int32),
-                ("v_water", ctypes.c_double)]
+                ("v_water", ctypes.c_double), ("misfit", ctypes.c_int32)]
+
+
+# Values of empso_geometry.misfit by the workload key "misfit".
+MISFITS = {"l2": 0, "trace_normalised": 1}
 
 
 class ProblemInfo(ctypes.Structure):
@@ -67,6 +71,8 @@ SIGNATURES = {
     "empso_gradient_workspace_bytes": (ctypes.c_size_t, [_vp, ctypes.c_int32]),
     "empso_gradient": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_int32, _vp, ctypes.c_size_t, _vp]),
     "empso_misfit": (ctypes.c_int, [_vp, _vp, ctypes.c_int64, _vp, _vp, ctypes.c_size_t, _vp]),
+    "empso_traces_misfit_workspace_bytes": (ctypes.c_size_t, [_vp, ctypes.c_int32]),
+    "empso_traces_misfit": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int32, _vp, _vp, ctypes.c_size_t, _vp]),
     "empso_fitness_workspace_bytes": (ctypes.c_size_t, [_P(_vp), ctypes.c_int32, _P(ctypes.c_int32),
                                                         ctypes.c_int32]),
     "empso_fitness_batch": (ctypes.c_int, [_P(_vp), ctypes.c_int32, _P(_vp), _P(ctypes.c_int32),

@@ -185,6 +185,8 @@ extern "C" int empso_problem_create(const empso_geometry *gp, empso_problem **ou
     }
     if (D64 > (1 << 20)) EMPSO_FAIL(EMPSO_ENOTSUP, "too many control nodes");
     if (g.water_rows < 0 || g.water_rows >= g.nz) EMPSO_FAIL(EMPSO_EINVAL, "water_rows must lie in [0, nz)");
+    if (g.misfit != EMPSO_MISFIT_L2 && g.misfit != EMPSO_MISFIT_TRACE_NORMALISED)
+        EMPSO_FAIL(EMPSO_EINVAL, "misfit must be EMPSO_MISFIT_L2 or EMPSO_MISFIT_TRACE_NORMALISED");
     if (!(g.dz > 0) || !(g.dx > 0) || !(g.dt > 0) || !(g.f0 > 0) || !std::isfinite(g.dz) ||
         !std::isfinite(g.dx) || !std::isfinite(g.dt) || !std::isfinite(g.f0))
         EMPSO_FAIL(EMPSO_EINVAL, "dz, dx, dt, f0 must be positive and finite");
@@ -407,11 +409,13 @@ struct RunDesc {
     const float *C;             // coefficient field of the particle
     const float *obs;           // [nt][nrec] observed traces of this shot (fitness mode)
     float *traces;              // [nt][nrec] output (record mode) or NULL
-    double *acc;                // [nrec] running sum of squared residuals
+    double *acc;                // l2: [nrec] running sum of squared residuals;
+                                // trace-normalised: [3][nrec] sums of d^2, d o, o^2
     const float *wav, *az, *ax;
     const int *recmap, *reccol;
     int Nz, Nx, S, nrec, recS, srcS, srcC, nt;
     int zlo, zhi;               // stored rows [zlo, zhi) have a_z = 0
+    int norm;                   // misfit: 0 l2, 1 trace-normalised
     unsigned fbytes;            // bytes of one stored field (u, v or C)
     float c0, cz1, cz2, cz3, cz4, cx1, cx2, cx3, cx4, wscale;
 };
@@ -535,6 +539,25 @@ __device__ __forceinline__ void bst4(rsrc_t r, int off, float4 v) {
     __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(v4u, w), r, off, 0, 0);
 }
 
+// Trace-normalised misfit: running sums of d^2, d o and o^2 of receiver r
+// (the sample products are exact in FP64).
+__device__ __forceinline__ void trace_sums(double *acc, int nrec, int r, float d, float o) {
+    const double dd = d, oo = o;
+    gst(acc + r, gld(acc + r) + dd * dd);
+    gst(acc + nrec + r, gld(acc + nrec + r) + dd * oo);
+    gst(acc + 2 * nrec + r, gld(acc + 2 * nrec + r) + oo * oo);
+}
+
+// Misfit of one trace from its sums: 1/2 |d/|d| - o/|o||^2 with a zero trace
+// kept zero. A non-finite modelled trace gives +inf.
+__device__ __forceinline__ double trace_normalised_misfit(double dd, double dov, double oo) {
+    if (!(dd < INFINITY) || dov != dov) return INFINITY;
+    const bool hd = dd > 0.0, ho = oo > 0.0;
+    double m = 0.5 * ((hd ? 1.0 : 0.0) + (ho ? 1.0 : 0.0));
+    if (hd && ho) m -= dov / (sqrt(dd) * sqrt(oo));
+    return fmax(m, 0.0);                            // a sum of squares; 1 - cos may round below 0
+}
+
 // Accumulate (or record) the receiver samples held by one lane: u4 are the
 // values of u^n at padded columns J0 .. J0+3 of the receiver row.
 __device__ __forceinline__ void sample_receivers(const RunDesc &R, int n, int J0, const float4 ce) {
@@ -548,9 +571,11 @@ __device__ __forceinline__ void sample_receivers(const RunDesc &R, int n, int J0
                 const size_t o = (size_t)n * R.nrec + r;
                 if (R.traces) {
                     gst(R.traces + o, u4[k]);
-                } else {
+                } else if (!R.norm) {
                     const float res = u4[k] - gld(R.obs + o);
                     gst(R.acc + r, gld(R.acc + r) + (double)res * (double)res);
+                } else {
+                    trace_sums(R.acc, R.nrec, r, u4[k], gld(R.obs + o));
                 }
             }
         }
@@ -782,14 +807,17 @@ __global__ void k_sample(const RunDesc *__restrict__ runs, int nruns, int n, int
         const size_t o = (size_t)n * R.nrec + r;
         if (R.traces) {
             R.traces[o] = val;
-        } else {
+        } else if (!R.norm) {
             const float res = val - R.obs[o];
             R.acc[r] += (double)res * (double)res;
+        } else {
+            trace_sums(R.acc, R.nrec, r, val, R.obs[o]);
         }
     }
 }
 
-// fitness[p] = 1/2 sum over the runs of particle p and their receivers of acc.
+// fitness[p] = sum over the runs of particle p and their receivers of the
+// trace misfit: 1/2 acc (l2) or the trace-normalised misfit of the sums.
 // Fixed per-thread order and a fixed tree: the result does not depend on tiling.
 __global__ __launch_bounds__(256) void k_fitness(const RunDesc *__restrict__ runs, const int *__restrict__ prun,
                                                  float *__restrict__ fitness) {
@@ -797,7 +825,9 @@ __global__ __launch_bounds__(256) void k_fitness(const RunDesc *__restrict__ run
     double s = 0.0;
     for (int run = prun[p]; run < prun[p + 1]; ++run) {
         const RunDesc &R = runs[run];
-        for (int r = threadIdx.x; r < R.nrec; r += blockDim.x) s += R.acc[r];
+        for (int r = threadIdx.x; r < R.nrec; r += blockDim.x)
+            s += R.norm ? trace_normalised_misfit(R.acc[r], R.acc[R.nrec + r], R.acc[2 * R.nrec + r])
+                        : 0.5 * R.acc[r];
     }
     __shared__ double red[256];
     red[threadIdx.x] = s;
@@ -807,7 +837,7 @@ __global__ __launch_bounds__(256) void k_fitness(const RunDesc *__restrict__ run
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        const double f = 0.5 * red[0];
+        const double f = red[0];
         fitness[p] = (f == f && f < 1e300) ? (float)f : INFINITY;
     }
 }
@@ -918,7 +948,8 @@ static Layout make_layout(const std::vector<const empso_problem *> &pp, const st
     L.acc_off = o;
     for (int k = 0; k < nruns; ++k) {
         L.acc_of_run.push_back(o);
-        o = align_up(o + sizeof(double) * runs[k].p->g.nrec, 256);
+        const size_t nsums = runs[k].p->g.misfit == EMPSO_MISFIT_TRACE_NORMALISED ? 3 : 1;
+        o = align_up(o + sizeof(double) * nsums * runs[k].p->g.nrec, 256);
     }
     L.total = o;
     return L;
@@ -1076,6 +1107,7 @@ static void build_header(Plan &pl, unsigned char *ws, const std::vector<const em
         d.Nz = p->Nz; d.Nx = p->Nx; d.S = p->S; d.nrec = p->g.nrec;
         d.recS = p->recI + kRing;
         d.zlo = p->zlo; d.zhi = p->zhi;
+        d.norm = (rs.obs && p->g.misfit == EMPSO_MISFIT_TRACE_NORMALISED) ? 1 : 0;
         d.srcS = p->srcI[rs.shot] + kRing;
         d.srcC = p->srcJ[rs.shot] + kRing;
         d.nt = p->g.nt;
@@ -1216,6 +1248,64 @@ extern "C" int empso_misfit(const float *a_d, const float *b_d, int64_t n, float
     const int nb = 1024;
     k_misfit_partial<<<nb, 256, 0, st>>>(a_d, b_d, n, reinterpret_cast<double *>(ws));
     k_misfit_final<<<1, 256, 0, st>>>(reinterpret_cast<const double *>(ws), nb, out_d);
+    EMPSO_HIP(hipGetLastError());
+    return EMPSO_OK;
+}
+
+// Misfit of each recorded trace (shot blockIdx.y, receiver r): FP64 sums
+// over time in order, as the fitness kernels accumulate them.
+__global__ __launch_bounds__(256) void k_trace_misfit(const float *__restrict__ d, const float *__restrict__ o,
+                                                      int nt, int nrec, int norm, double *__restrict__ per) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrec) return;
+    const size_t base = (size_t)blockIdx.y * nt * nrec + r;
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int n = 0; n < nt; ++n) {
+        const float dv = d[base + (size_t)n * nrec], ov = o[base + (size_t)n * nrec];
+        if (norm) {
+            a += (double)dv * dv;
+            b += (double)dv * ov;
+            c += (double)ov * ov;
+        } else {
+            const float res = dv - ov;
+            a += (double)res * (double)res;
+        }
+    }
+    per[(size_t)blockIdx.y * nrec + r] = norm ? trace_normalised_misfit(a, b, c) : 0.5 * a;
+}
+
+// out = sum of n values in a fixed order; not finite -> +inf.
+__global__ __launch_bounds__(256) void k_sum_final(const double *__restrict__ v, int64_t n, float *out) {
+    double s = 0.0;
+    for (int64_t k = threadIdx.x; k < n; k += blockDim.x) s += v[k];
+    __shared__ double red[256];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = (red[0] == red[0] && red[0] < 1e300) ? (float)red[0] : INFINITY;
+}
+
+extern "C" size_t empso_traces_misfit_workspace_bytes(const empso_problem *p, int32_t nsh) {
+    if (!p || nsh < 0) return 0;
+    return align_up(sizeof(double) * (size_t)std::max(nsh, 1) * p->g.nrec, 256);
+}
+
+extern "C" int empso_traces_misfit(const empso_problem *p, const float *traces_d, const float *obs_d, int32_t nsh,
+                                   float *out_d, void *ws, size_t ws_bytes, empso_stream stream) {
+    clear_error();
+    if (!p || !out_d || !ws || (nsh > 0 && (!traces_d || !obs_d))) EMPSO_FAIL(EMPSO_EINVAL, "NULL argument");
+    if (nsh < 0) EMPSO_FAIL(EMPSO_EINVAL, "nsh must be >= 0");
+    if (ws_bytes < empso_traces_misfit_workspace_bytes(p, nsh)) EMPSO_FAIL(EMPSO_EWORKSPACE, "workspace too small");
+    hipStream_t st = (hipStream_t)stream;
+    double *per = reinterpret_cast<double *>(ws);
+    const int nrec = p->g.nrec;
+    if (nsh > 0)
+        k_trace_misfit<<<dim3((nrec + 255) / 256, nsh), 256, 0, st>>>(
+            traces_d, obs_d, p->g.nt, nrec, p->g.misfit == EMPSO_MISFIT_TRACE_NORMALISED ? 1 : 0, per);
+    k_sum_final<<<1, 256, 0, st>>>(per, (int64_t)nsh * nrec, out_d);
     EMPSO_HIP(hipGetLastError());
     return EMPSO_OK;
 }
@@ -1531,7 +1621,9 @@ namespace {
 struct GradRun {
     float *fields;              // the run's fields, gfs floats apart
     const float *obs;           // [nt][nrec]
-    double *acc;                // [nrec] sum of squared residuals over k >= 1
+    double *acc;                // [nrec] sum of squared residuals over k >= 1 (l2)
+    double *tsum;               // trace-normalised: [3][nrec] sums of d^2, d o, o^2; else NULL
+    float *ab;                  // trace-normalised: [2][nrec] adjoint-source weights alpha, beta
     int srcS, srcC;             // stored row and column of the source
 };
 
@@ -1563,15 +1655,18 @@ static int grad_interval(const empso_problem *p, int K) {
 
 // One time step of every run: out = cur + d with
 // d = [(1-a)(cur - prev) + C (Lap cur + s)] / (1+a). Forward (ADJ = false):
-// s = fsrc at the source point. Adjoint (ADJ = true): s = u^k - d^k at the
-// receivers (accumulated into the misfit), and the gradient accumulator takes
+// s = fsrc at the source point; with tsample set, the receivers add u^{k+1}^2
+// and u^{k+1} d^{k+1} to the trace sums. Adjoint (ADJ = true): s is the
+// derivative of the misfit with respect to u^k at the receivers, u^k - d^k
+// (l2, accumulated into the misfit) or alpha u^k - beta d^k (trace-normalised),
+// and the gradient accumulator takes
 // out * [(1+a)(u^k - u^{k-1}) - (1-a)(u^{k-1} - u^{k-2})].
 // Thread (x, y) of block (bx, by, run) updates columns 4 (64 bx + x) .. +3 of
 // padded row 4 by + y.
 template <bool ADJ, bool ISO>
 __global__ __launch_bounds__(256) void k_gstep(const GradRun *__restrict__ runs, const GradShared sh, int cur,
                                                int prev, int out, float fsrc, int k, int uk, int uk1, int uk2,
-                                               int gacc, int illum) {
+                                               int gacc, int illum, int tsample) {
     const int I = blockIdx.y * 4 + (int)threadIdx.y;
     const int J0 = 4 * (blockIdx.x * 64 + (int)threadIdx.x);
     if (I >= sh.Nz || J0 >= sh.Nx) return;
@@ -1630,9 +1725,14 @@ __global__ __launch_bounds__(256) void k_gstep(const GradRun *__restrict__ runs,
         } else if (s == sh.recS && J < sh.Nx) {
             const int r = sh.recmap[J];
             if (r >= 0) {
-                res[q] = ukv[q] - R.obs[(size_t)k * sh.nrec + r];
+                const float ob = R.obs[(size_t)k * sh.nrec + r];
+                if (R.ab) {
+                    res[q] = fmaf(R.ab[r], ukv[q], -R.ab[sh.nrec + r] * ob);
+                } else {
+                    res[q] = ukv[q] - ob;
+                    R.acc[r] += (double)res[q] * (double)res[q];
+                }
                 lap += res[q];
-                R.acc[r] += (double)res[q] * (double)res[q];
             }
         }
         (void)res;
@@ -1640,6 +1740,14 @@ __global__ __launch_bounds__(256) void k_gstep(const GradRun *__restrict__ runs,
         const float d = fmaf(Cv[q], lap, (1.0f - a) * (u - pv[q])) * __builtin_amdgcn_rcpf(1.0f + a);
         const float un = u + d;
         R.fields[(size_t)out * sh.gfs + o + q] = un;
+        if (!ADJ && tsample && s == sh.recS && J < sh.Nx) {
+            const int r = sh.recmap[J];
+            if (r >= 0) {
+                const double dv = un, ov = R.obs[(size_t)(k + 1) * sh.nrec + r];
+                R.tsum[r] += dv * dv;
+                R.tsum[sh.nrec + r] += dv * ov;
+            }
+        }
         if (ADJ) {
             const float u0 = (&Uk4.x)[q], u1 = (&Uk14.x)[q], u2 = (&Uk24.x)[q];
             float *g = R.fields + (size_t)gacc * sh.gfs + o + q;
@@ -1686,13 +1794,54 @@ __global__ void k_gfold(const GradRun *__restrict__ runs, int nruns, const GradS
     }
 }
 
-// J = 1/2 sum over runs and receivers of (sum_{k>=1} r^k^2 + d^0^2) (u^0 = 0).
-__global__ __launch_bounds__(256) void k_gmisfit(const GradRun *__restrict__ runs, int nruns, int nrec, float *out) {
+// Trace-normalised misfit: sum over n of d^n_r^2 per run and receiver into
+// the third block of the trace sums (one block per run).
+__global__ __launch_bounds__(256) void k_gobs2(const GradRun *__restrict__ runs, int nrec, int nt) {
+    const GradRun R = runs[blockIdx.x];
+    for (int r = threadIdx.x; r < nrec; r += blockDim.x) {
+        double s = 0.0;
+        for (int n = 0; n < nt; ++n) {
+            const double o = R.obs[(size_t)n * nrec + r];
+            s += o * o;
+        }
+        R.tsum[2 * nrec + r] = s;
+    }
+}
+
+// Adjoint-source weights of the trace-normalised misfit m = 1/2 |d/|d| - o/|o||^2:
+// dm/dd = alpha d - beta o with c = d.o / (|d| |o|), alpha = c / |d|^2,
+// beta = 1 / (|d| |o|); both zero when either trace is zero (m is then
+// constant in d, or not differentiable at d = 0).
+__global__ __launch_bounds__(256) void k_gab(const GradRun *__restrict__ runs, int nrec) {
+    const GradRun R = runs[blockIdx.x];
+    for (int r = threadIdx.x; r < nrec; r += blockDim.x) {
+        const double dd = R.tsum[r], dov = R.tsum[nrec + r], oo = R.tsum[2 * nrec + r];
+        float al = 0.0f, be = 0.0f;
+        if (dd > 0.0 && oo > 0.0 && dd < INFINITY) {
+            const double dn = sqrt(dd), on = sqrt(oo);
+            const double c = dov / (dn * on);
+            al = (float)(c / dd);
+            be = (float)(1.0 / (dn * on));
+        }
+        R.ab[r] = al;
+        R.ab[nrec + r] = be;
+    }
+}
+
+// J = sum over runs and receivers of the trace misfit: l2 1/2 (sum_{k>=1}
+// r^k^2 + d^0^2) (u^0 = 0), or the trace-normalised misfit of the sums.
+__global__ __launch_bounds__(256) void k_gmisfit(const GradRun *__restrict__ runs, int nruns, int nrec, int norm,
+                                                 float *out) {
     double s = 0.0;
     for (int r = 0; r < nruns; ++r)
         for (int q = threadIdx.x; q < nrec; q += blockDim.x) {
-            const double d0 = runs[r].obs[q];
-            s += runs[r].acc[q] + d0 * d0;
+            if (norm) {
+                const double *t = runs[r].tsum;
+                s += trace_normalised_misfit(t[q], t[nrec + q], t[2 * nrec + q]);
+            } else {
+                const double d0 = runs[r].obs[q];
+                s += 0.5 * (runs[r].acc[q] + d0 * d0);
+            }
         }
     __shared__ double red[256];
     red[threadIdx.x] = s;
@@ -1701,12 +1850,12 @@ __global__ __launch_bounds__(256) void k_gmisfit(const GradRun *__restrict__ run
         if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[0] = (float)(0.5 * red[0]);
+    if (threadIdx.x == 0) out[0] = (float)red[0];
 }
 
 struct GradLayout {
     GradSlots sl;
-    size_t fb, runs_off, cd_off, acc_off, C_off, fields_off, total;
+    size_t fb, runs_off, cd_off, acc_off, tsum_off, ab_off, C_off, fields_off, total;
 };
 
 static GradLayout grad_layout(const empso_problem *p, int K) {
@@ -1720,6 +1869,9 @@ static GradLayout grad_layout(const empso_problem *p, int K) {
     L.runs_off = take(sizeof(GradRun) * ns);
     L.cd_off = take(sizeof(CoefDesc));
     L.acc_off = take(sizeof(double) * (size_t)ns * p->g.nrec);
+    const bool norm = p->g.misfit == EMPSO_MISFIT_TRACE_NORMALISED;
+    L.tsum_off = take(norm ? sizeof(double) * 3 * (size_t)ns * p->g.nrec : 0);
+    L.ab_off = take(norm ? sizeof(float) * 2 * (size_t)ns * p->g.nrec : 0);
     L.C_off = take(L.fb);
     L.fields_off = take(L.fb * (size_t)L.sl.total() * ns);
     L.total = k;
@@ -1753,6 +1905,7 @@ extern "C" int empso_gradient(const empso_problem *p, const float *vp_d, const f
 
     unsigned char *w = reinterpret_cast<unsigned char *>(ws);
     const int ns = p->g.nshots, nt = p->g.nt;
+    const bool norm = p->g.misfit == EMPSO_MISFIT_TRACE_NORMALISED;
     const GradSlots &sl = L.sl;
     const size_t gfs = L.fb / sizeof(float);
     std::vector<GradRun> hr(ns);
@@ -1760,6 +1913,8 @@ extern "C" int empso_gradient(const empso_problem *p, const float *vp_d, const f
         hr[s].fields = reinterpret_cast<float *>(w + L.fields_off + L.fb * (size_t)sl.total() * s);
         hr[s].obs = obs_d + (size_t)s * nt * p->g.nrec;
         hr[s].acc = reinterpret_cast<double *>(w + L.acc_off) + (size_t)s * p->g.nrec;
+        hr[s].tsum = norm ? reinterpret_cast<double *>(w + L.tsum_off) + (size_t)3 * s * p->g.nrec : nullptr;
+        hr[s].ab = norm ? reinterpret_cast<float *>(w + L.ab_off) + (size_t)2 * s * p->g.nrec : nullptr;
         hr[s].srcS = p->srcI[s] + kRing;
         hr[s].srcC = p->srcJ[s] + kRing;
     }
@@ -1793,34 +1948,42 @@ extern "C" int empso_gradient(const empso_problem *p, const float *vp_d, const f
     // the source value of step n is wavelet[n] / (dz dx), read on the host
     std::vector<float> wav(nt);
     EMPSO_HIP(hipMemcpy(wav.data(), p->d_wav, sizeof(float) * nt, hipMemcpyDeviceToHost));
-    auto step_fwd = [&](int n, int cur, int prev, int out) {
+    auto step_fwd = [&](int n, int cur, int prev, int out, int tsample) {
         const float fs = wav[n] * p->wscale;
         if (iso)
-            k_gstep<false, true><<<grd, blk, 0, st>>>(runs, sh, cur, prev, out, fs, n, 0, 0, 0, 0, 0);
+            k_gstep<false, true><<<grd, blk, 0, st>>>(runs, sh, cur, prev, out, fs, n, 0, 0, 0, 0, 0, tsample);
         else
-            k_gstep<false, false><<<grd, blk, 0, st>>>(runs, sh, cur, prev, out, fs, n, 0, 0, 0, 0, 0);
+            k_gstep<false, false><<<grd, blk, 0, st>>>(runs, sh, cur, prev, out, fs, n, 0, 0, 0, 0, 0, tsample);
     };
     auto step_adj = [&](int k, int cur, int prev, int out, int uk, int uk1, int uk2) {
         if (iso)
             k_gstep<true, true><<<grd, blk, 0, st>>>(runs, sh, cur, prev, out, 0.0f, k, uk, uk1, uk2, sl.gacc(),
-                                                     illum_d != nullptr);
+                                                     illum_d != nullptr, 0);
         else
             k_gstep<true, false><<<grd, blk, 0, st>>>(runs, sh, cur, prev, out, 0.0f, k, uk, uk1, uk2, sl.gacc(),
-                                                      illum_d != nullptr);
+                                                      illum_d != nullptr, 0);
     };
     auto copy = [&](int src, int dst) { k_gcopy<<<dim3(cblocks, ns), 256, 0, st>>>(runs, gfs, src, dst); };
 
-    // forward pass over n = 0 .. nt-2 with u^n in ring slot (n mod 3); the
-    // checkpoint j holds (u^{jK}, u^{jK-1}) for every jK <= nt - 2
+    // forward pass with u^n in ring slot (n mod 3); the checkpoint j holds
+    // (u^{jK}, u^{jK-1}) for every jK <= nt - 2. The l2 misfit needs the pass
+    // up to the last checkpoint only; the trace-normalised one needs whole
+    // traces (their norms) before the adjoint starts, so it runs all steps,
+    // sampling the receivers, and then forms the adjoint-source weights.
     const int K = sl.K, last = sl.ncheck - 1;
     auto ring = [](int n) { return ((n % 3) + 3) % 3; };
-    for (int n = 0; n < last * K; ++n) {
-        step_fwd(n, ring(n), ring(n - 1), ring(n + 1));
-        if ((n + 1) % K == 0) {
+    const int nfwd = norm ? nt - 1 : last * K;
+    for (int n = 0; n < nfwd; ++n) {
+        step_fwd(n, ring(n), ring(n - 1), ring(n + 1), norm ? 1 : 0);
+        if ((n + 1) % K == 0 && (n + 1) / K <= last) {
             const int j = (n + 1) / K;
             copy(ring(n + 1), sl.ck(j, 0));
             copy(ring(n), sl.ck(j, 1));
         }
+    }
+    if (norm) {
+        k_gobs2<<<ns, 256, 0, st>>>(runs, p->g.nrec, nt);
+        k_gab<<<ns, 256, 0, st>>>(runs, p->g.nrec);
     }
     // backward pass, segment by segment: segment j covers u^{jK-1} .. u^{e}
     // in slots 0 .. e - jK + 1 (checkpoint 0 is the zero initial state)
@@ -1833,14 +1996,14 @@ extern "C" int empso_gradient(const empso_problem *p, const float *vp_d, const f
             copy(sl.ck(0, 1), sl.seg(0));                 // zero fields
             copy(sl.ck(0, 0), sl.seg(1));
         }
-        for (int n = b; n < e; ++n) step_fwd(n, sl.seg(n - b + 1), sl.seg(n - b), sl.seg(n - b + 2));
+        for (int n = b; n < e; ++n) step_fwd(n, sl.seg(n - b + 1), sl.seg(n - b), sl.seg(n - b + 2), 0);
         for (int k = e; k >= b + 1; --k)
             step_adj(k, sl.adj(k + 1), sl.adj(k + 2), sl.adj(k), sl.seg(k - b + 1), sl.seg(k - b), sl.seg(k - b - 1));
     }
     const int64_t npts = (int64_t)p->g.nz * p->g.nx;
     k_gfold<<<(int)std::min<int64_t>(2048, (npts + 255) / 256), 256, 0, st>>>(runs, ns, sh, sl.gacc(), vp_d, p->g.nz,
                                                                               p->g.nx, p->g.nbl, p->g.dt, grad_d, illum_d);
-    k_gmisfit<<<1, 256, 0, st>>>(runs, ns, p->g.nrec, misfit_d);
+    k_gmisfit<<<1, 256, 0, st>>>(runs, ns, p->g.nrec, norm ? 1 : 0, misfit_d);
     EMPSO_HIP(hipGetLastError());
     return EMPSO_OK;
 }

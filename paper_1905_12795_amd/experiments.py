@@ -76,8 +76,8 @@ def throughput(workload, particles, calls):
            "grids": [[p.info.Nz, p.info.Nx] for p in probs], "nt": probs[0].nt})
 
 
-def surrogate(workload, iters, seeds, K, log, members=1, kappa=0.0):
-    g = config(workload)
+def surrogate(workload, iters, seeds, K, log, members=1, kappa=0.0, misfit="l2"):
+    g = dict(config(workload), misfit=misfit)
     if workload in ("realistic", "irregular", "crime_free"):
         g = dict(g)
         g["particles"] = config("surrogate")["particles"]      # 64 particles x K = 16 -> 1024 candidates
@@ -85,7 +85,8 @@ def surrogate(workload, iters, seeds, K, log, members=1, kappa=0.0):
     dobs = search.observed_for(g, prob, true_model(g))
     hist = {m: [] for m in ("plain", "screened", "random")}
     for seed in seeds:
-        res = {"workload": workload, "seed": seed, "particles": g["particles"], "K": K, "iterations": iters}
+        res = {"workload": workload, "misfit": misfit, "seed": seed, "particles": g["particles"], "K": K,
+               "iterations": iters}
         hp = search.run(g, dobs, prob, iters, "plain", seed=seed, log_path=log)
         hist["plain"].append(hp)
         target = 1.01 * hp[-1]["best"]
@@ -103,7 +104,7 @@ def surrogate(workload, iters, seeds, K, log, members=1, kappa=0.0):
     # seed-averaged best-misfit curves: a single search is chaotic
     mean = {m: search.mean_history(h) for m, h in hist.items()}
     target = 1.01 * mean["plain"][-1]["best"]
-    summ = {"workload": workload, "seeds": list(seeds), "summary": "seed-averaged best-misfit curves",
+    summ = {"workload": workload, "misfit": misfit, "seeds": list(seeds), "summary": "seed-averaged best-misfit curves",
             "plain_final": mean["plain"][-1]["best"], "plain_evals": mean["plain"][-1]["evaluations"],
             "plain_wall": mean["plain"][-1]["wall_s"]}
     for mode in ("screened", "random"):
@@ -114,10 +115,10 @@ def surrogate(workload, iters, seeds, K, log, members=1, kappa=0.0):
     _emit(summ)
 
 
-def local_fwi(workload, search_iters, fwi_iters, seed):
+def local_fwi(workload, search_iters, fwi_iters, seed, misfit="l2"):
     """The paper's workflow: the EMPSO best model starts a local FWI of the same data."""
     from paper_1905_12795_amd import fwi
-    g = config(workload)
+    g = dict(config(workload), misfit=misfit)
     prob = fd.Problem(g)
     truth = true_model(g)
     dobs = search.observed_for(g, prob, truth)
@@ -128,7 +129,9 @@ def local_fwi(workload, search_iters, fwi_iters, seed):
     t0 = time.perf_counter()
     v, hist = fwi.invert(prob, dobs, v0, fwi_iters, log=lambda r: _emit({"stage": "fwi", **r}))
     torch.cuda.synchronize()
-    _emit({"workload": workload, "seed": seed, "empso_misfit": h[-1]["best"], "fwi_misfit": hist[-1]["misfit"],
+    _emit({"workload": workload, "misfit": misfit, "seed": seed, "empso_misfit": h[-1]["best"],
+           "true_model_misfit": fwi.model_misfit(prob, torch.tensor(truth, dtype=torch.float32, device="cuda"), dobs),
+           "fwi_misfit": hist[-1]["misfit"],
            "fwi_iterations": len(hist) - 1, "fwi_wall_s": time.perf_counter() - t0,
            "rms_error_empso": fwi.rms_error(v0.cpu().numpy(), truth), "rms_error_fwi": fwi.rms_error(v, truth)})
 
@@ -197,11 +200,13 @@ def main():
     s.add_argument("--log", default=None)
     s.add_argument("--members", type=int, default=1, help="networks in the surrogate ensemble")
     s.add_argument("--kappa", type=float, default=0.0, help="score = members' mean + kappa * spread")
+    s.add_argument("--misfit", default="l2", choices=["l2", "trace_normalised"])
     f = sub.add_parser("fwi")
     f.add_argument("--workload", default="realistic", choices=["realistic", "irregular", "crime_free"])
     f.add_argument("--search-iters", type=int, default=15)
     f.add_argument("--fwi-iters", type=int, default=10)
     f.add_argument("--seed", type=int, default=1)
+    f.add_argument("--misfit", default="l2", choices=["l2", "trace_normalised"])
     gr = sub.add_parser("gradient")
     gr.add_argument("--workload", default="realistic", choices=["tiny", "realistic", "irregular", "crime_free", "full"])
     gr.add_argument("--reps", type=int, default=2)
@@ -216,9 +221,10 @@ def main():
     elif a.cmd == "mlp":
         mlp_timing(a.reps)
     elif a.cmd == "fwi":
-        local_fwi(a.workload, a.search_iters, a.fwi_iters, a.seed)
+        local_fwi(a.workload, a.search_iters, a.fwi_iters, a.seed, a.misfit)
     else:
-        surrogate(a.workload, a.iters, [int(x) for x in a.seeds.split(",")], a.K, a.log, a.members, a.kappa)
+        surrogate(a.workload, a.iters, [int(x) for x in a.seeds.split(",")], a.K, a.log, a.members, a.kappa,
+                  a.misfit)
 
 
 if __name__ == "__main__":

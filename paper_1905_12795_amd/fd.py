@@ -10,7 +10,7 @@ import math
 import numpy as np
 import torch
 
-from ._lib import Geometry, ProblemInfo, Tuning, check, lib
+from ._lib import MISFITS, Geometry, ProblemInfo, Tuning, check, lib
 
 
 def _stream():
@@ -96,6 +96,10 @@ class Problem:
             g.level_nodes = self._nn_.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
             g.node_x = self._nx_.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         g.water_rows, g.v_water = water_rows, v_water
+        self.misfit = geom.get("misfit", "l2")
+        if self.misfit not in MISFITS:
+            raise ValueError("misfit must be one of %s" % sorted(MISFITS))
+        g.misfit = MISFITS[self.misfit]
         h = ctypes.c_void_p()
         check(lib.empso_problem_create(ctypes.byref(g), ctypes.byref(h)))
         self.handle = h
@@ -188,6 +192,22 @@ def misfit(a, b, out=None, ws=None):
     if ws is None:
         ws = workspace(lib.empso_misfit_workspace_bytes(n), a.device)
     check(lib.empso_misfit(_ptr(a), _ptr(b), n, _ptr(out), _ptr(ws), ws.numel(), _stream()))
+    return out
+
+
+def traces_misfit(prob, traces, obs, out=None, ws=None):
+    """The problem's misfit (l2 or trace-normalised) between recorded traces
+    and observed traces, both device FP32 [nsh][nt][nrec], summed over shots
+    (library call) -> tensor [1]."""
+    nsh = traces.shape[0] if traces.dim() == 3 else -1
+    _need(traces, torch.float32, (nsh, prob.nt, prob.nrec), "traces")
+    _need(obs, torch.float32, (nsh, prob.nt, prob.nrec), "obs")
+    if out is None:
+        out = torch.empty(1, dtype=torch.float32, device=traces.device)
+    if ws is None:
+        ws = workspace(lib.empso_traces_misfit_workspace_bytes(prob.handle, nsh), traces.device)
+    check(lib.empso_traces_misfit(prob.handle, _ptr(traces), _ptr(obs), nsh, _ptr(out), _ptr(ws), ws.numel(),
+                                  _stream()))
     return out
 
 

@@ -2,7 +2,8 @@
 
 Paper, Testing approach and Results sections: the best EMPSO model is the
 starting model of a local FWI of the same data with the same l2 misfit,
-run from low to higher frequencies. Here: steepest descent on the grid
+run from low to higher frequencies (the trace-normalised misfit, when the
+problem selects it, goes through the same calls). Here: steepest descent on the grid
 model with the exact gradient of the discrete misfit (empso_gradient),
 Barzilai-Borwein step lengths, a backtracking (Armijo) line search and a
 box projection onto [vmin, vmax]; the model update is host FP64 arithmetic
@@ -19,9 +20,10 @@ from . import fd
 
 
 def model_misfit(prob, vp, obs):
-    """Misfit of a physical model (device FP32 [nz][nx]) over all shots."""
+    """The problem's misfit (l2 or trace-normalised) of a physical model
+    (device FP32 [nz][nx]) over all shots."""
     tr = fd.forward_shots(prob, vp)
-    return float(fd.misfit(tr, obs))
+    return float(fd.traces_misfit(prob, tr, obs))
 
 
 def invert(prob, obs, vp0, iterations, vmin=None, vmax=None, first_step=20.0, armijo=1e-4, max_trials=8,

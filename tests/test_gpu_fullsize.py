@@ -196,3 +196,28 @@ def test_crime_free_observed_data(gfd):
     _say("crime-free: true-model residual %.3f of the data, misfit true %.4g prior %.4g" % (rel_true, f_true, f_prior))
     assert rel_true > 0.01
     assert f_true < f_prior
+
+
+@pytest.mark.timeout(600)
+def test_crime_free_trace_normalised_full_size_sampled(gfd):
+    """The crime-free data scored with the trace-normalised misfit at full
+    size: the whole batch on the GPU, the prior-mean particle by the oracle
+    (all 16 shots), and the true model's misfit below the prior's."""
+    from paper_1905_12795_amd import search
+    g = dict(config("crime_free"), misfit="trace_normalised")
+    prob = gfd.Problem(g)
+    op = ofd.Problem(g, dt=prob.dt, nt=prob.nt)
+    vp = true_model(g)
+    dobs = search.observed_for(g, prob, vp)
+    X = uniform_particles(4, g["node_lo"], g["node_hi"], g["particle_seed"])
+    X[0] = 0.5 * (g["node_lo"] + g["node_hi"])
+    fg = gfd.FitnessBatch([prob], [dobs], [0] * 4)(X).cpu().numpy().astype(np.float64)
+    t0 = time.time()
+    fo, _ = ofd.fitness_batch(op, X[[0]].astype(np.float32).astype(np.float64), dobs.cpu().numpy())
+    ntr = op.nshots * op.nrec
+    _say("trace-normalised prior: gpu %.6g oracle %.6g (%.1fs); batch %s" % (fg[0], fo[0], time.time() - t0, fg))
+    assert abs(fg[0] - fo[0]) <= REL * fo[0]
+    f_true = float(gfd.traces_misfit(prob, gfd.forward_shots(prob, torch.tensor(vp, dtype=torch.float32,
+                                                                                 device="cuda")), dobs))
+    _say("trace-normalised true model %.6g of %d traces" % (f_true, ntr))
+    assert f_true < fg[0]

@@ -96,6 +96,8 @@ def _geom(L, **kw):
     (dict(water_rows=101), -1),                                             # water_rows >= nz
     (dict(water_rows=-1), -1),
     (dict(water_rows=4, v_water=1000.0), -1),                               # water velocity below vmin
+    (dict(misfit=2), -1),                                                   # unknown misfit
+    (dict(misfit=-1), -1),
 ])
 def test_problem_create_rejects_on_host(L, kw, status):
     g = _geom(L, **kw)
@@ -126,3 +128,19 @@ def test_empty_batch_is_a_no_op(L):
 def test_gradient_null_arguments(L):
     assert L.lib.empso_gradient_workspace_bytes(None, 0) == 0
     assert L.lib.empso_gradient(None, None, None, None, None, None, 0, None, 0, None) == -1
+
+
+def test_traces_misfit_null_arguments(L):
+    assert L.lib.empso_traces_misfit_workspace_bytes(None, 1) == 0
+    assert L.lib.empso_traces_misfit(None, None, None, 0, None, None, 0, None) == -1
+
+
+def test_geometry_struct_matches_the_header(L):
+    """The binding's struct ends with the misfit selector, after v_water."""
+    hdr = open(os.path.join(os.path.dirname(__file__), "..", "include", "empso.h")).read()
+    body = hdr[hdr.index("typedef struct {\n    int32_t nz, nx;"):hdr.index("} empso_geometry;")]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    names = re.findall(r"(\w+)\s*[,;]", body)
+    assert names == [f for f, _ in L.Geometry._fields_]
+    assert (L.MISFITS["l2"], L.MISFITS["trace_normalised"]) == (0, 1)
+    assert "#define EMPSO_MISFIT_L2 0" in hdr and "#define EMPSO_MISFIT_TRACE_NORMALISED 1" in hdr
