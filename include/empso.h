@@ -109,19 +109,25 @@ typedef struct {
     const double *node_x;
     int32_t water_rows;      /* physical rows 0 .. water_rows-1 hold v_water (either grid) */
     double v_water;          /* within [vmin, vmax] when water_rows > 0                  */
-    /* Misfit of empso_fitness_batch (EMPSO_MISFIT_*). The paper scores
-     * fitness with the l2 misfit (Testing approach section). The optional
-     * trace-normalised variant divides every trace (one receiver of one shot,
-     * over the nt samples) of the modelled and of the observed data by its own
-     * l2 norm before the l2 misfit (a zero trace stays zero), which removes
-     * amplitude mismatches between modelled and recorded sources: per trace
-     * 1/2 |d/|d| - o/|o||^2 = 1 - d.o / (|d| |o|) when both are non-zero,
-     * 1/2 when exactly one is zero, 0 when both are. Same validation as l2. */
+    /* Misfit of empso_fitness_batch, empso_gradient and empso_traces_misfit
+     * (EMPSO_MISFIT_*). The paper scores fitness with the l2 misfit (Testing
+     * approach section). The optional trace-normalised variant divides every
+     * trace (one receiver of one shot, over the nt samples) of the modelled
+     * and of the observed data by max(its l2 norm, w) before the l2 misfit,
+     * w = EMPSO_TRACE_FLOOR times the largest trace norm of the same shot on
+     * the same side (modelled or observed; a trace divided by zero stays
+     * zero). This removes amplitude mismatches between modelled and
+     * recorded sources: each side is invariant under a scale of all its
+     * traces. The floor keeps traces that no arrival reaches (the scheme's
+     * numerical precursor, orders of magnitude below any arrival) from being
+     * raised to full weight. Per trace above both floors:
+     * 1/2 |d/|d| - o/|o||^2 = 1 - d.o / (|d| |o|). */
     int32_t misfit;
 } empso_geometry;
 
 #define EMPSO_MISFIT_L2 0
 #define EMPSO_MISFIT_TRACE_NORMALISED 1
+#define EMPSO_TRACE_FLOOR 1e-4
 
 /* Read-only facts about a problem (for sizing caller-owned arrays). */
 typedef struct {

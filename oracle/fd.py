@@ -21,10 +21,13 @@ Conventions the paper leaves open, and the reading taken here:
     halved; the search only compares misfits, so any increasing transform
     leaves it unchanged). Optional variant (geometry key "misfit" =
     "trace_normalised"): every trace, one receiver of one shot over time, of
-    the modelled and of the observed data is divided by its own l2 norm (a
-    zero trace stays zero) before that misfit. The paper states the plain l2
-    norm; the normalisation is the usual remedy for a source whose amplitude
-    the modelling does not know.
+    the modelled and of the observed data is divided by its own l2 norm, or
+    by a floor of 1e-4 times the largest trace norm of the same shot and side
+    (modelled or observed) where that is larger (a zero trace stays zero),
+    before that misfit. The paper states the plain l2 norm; the
+    normalisation is the usual remedy for a source whose amplitude the
+    modelling does not know, and the floor keeps traces with no arrival from
+    being raised to full weight.
   * control nodes form a regular ncz x ncx grid whose corners are the corners
     of the physical grid; the padded layer copies the nearest physical value.
   * the paper's irregular node grid (Testing approach section: nodes built
@@ -467,20 +470,37 @@ def unpad_adjoint(g_pad, nbl):
 
 
 def normalised_adjoint_data(d, o):
-    """Data o' for which the l2 residual d - o' is the derivative of the
-    trace-normalised misfit with respect to the modelled traces d:
-    m = 1/2 |d/|d| - o/|o||^2 has dm/dd = (d/|d|) c / |d| - o / (|d| |o|),
-    c = d.o / (|d| |o|), so o' = d - dm/dd (per trace; zero where either
-    trace is zero: m is then constant in d, or not differentiable at d = 0)."""
+    """Data o' of one shot ([nt][nrec]) for which the l2 residual d - o' is
+    the derivative of the trace-normalised misfit, the sum over traces of
+    m_r = 1/2 |d_r/s_r - o_hat_r|^2 (s_r = max(|d_r|, w), w the modelled
+    floor, o_hat the normalised observed traces), with respect to the
+    modelled traces d:
+      * above the floor (|d_r| > w) d_r/|d_r| has the Jacobian
+        (I - e e^T)/|d_r|, e = d_r/|d_r|: dm_r/dd_r = (I - e e^T)(e - o_hat_r)/|d_r|;
+      * at or below it s_r = w: dm_r/dd_r = (d_r/w - o_hat_r)/w, and m_r also
+        depends on w = TRACE_FLOOR |d_k| (k the largest modelled trace) with
+        dm_r/dw = -d_r . (d_r/w - o_hat_r) / w^2, which adds
+        TRACE_FLOOR (sum of those) d_k/|d_k| to the derivative for trace k.
+    o' = d - dm/dd."""
     d = np.asarray(d, dtype=np.float64)
     o = np.asarray(o, dtype=np.float64)
-    dn = np.sqrt(np.sum(d * d, axis=0))
-    on = np.sqrt(np.sum(o * o, axis=0))
-    ok = (dn > 0) & (on > 0)
-    dns, ons = np.where(ok, dn, 1.0), np.where(ok, on, 1.0)
-    c = np.sum(d * o, axis=0) / (dns * ons)
-    grad_d = np.where(ok, d * (c / dns ** 2) - o / (dns * ons), 0.0)
-    return d - grad_d
+    w = trace_floor(d)
+    oh = normalise_traces(o, trace_floor(o))
+    norms = np.sqrt(np.sum(d * d, axis=0))
+    g = np.zeros_like(d)
+    dm_dw = 0.0
+    for r in range(d.shape[1]):
+        x, y, n = d[:, r], oh[:, r], float(norms[r])
+        if n > w:
+            e = x / n
+            g[:, r] = ((e - y) - e * np.dot(e, e - y)) / n
+        elif w > 0:
+            g[:, r] = (x / w - y) / w
+            dm_dw -= np.dot(x, x / w - y) / w ** 2
+    if w > 0:
+        k = int(np.argmax(norms))
+        g[:, k] += TRACE_FLOOR * dm_dw * d[:, k] / norms[k]
+    return d - g
 
 
 def gradient(prob, vp, d_obs, shots=None, threads=None):
@@ -531,19 +551,40 @@ def misfit(a, b):
     return 0.5 * float(np.sum(r * r))
 
 
-def normalise_traces(d):
-    """Each trace (time axis -2, receivers on axis -1) divided by its l2 norm;
-    a zero trace stays zero."""
+# Relative floor of the trace normalisation: a trace is divided by
+# max(|trace|, w) with w = TRACE_FLOOR times the largest trace norm of the
+# same shot's traces on the same side (modelled or observed), so that traces
+# with no arrival (the scheme's precursor alone, many orders of magnitude
+# below any arrival) are not raised to full weight, and each side stays
+# invariant under a scale of all its traces.
+TRACE_FLOOR = 1e-4
+
+
+def trace_floor(x):
+    """w of one shot's traces x[nt][nrec]."""
+    x = np.asarray(x, dtype=np.float64)
+    return TRACE_FLOOR * float(np.sqrt(np.sum(x * x, axis=0)).max())
+
+
+def normalise_traces(d, w):
+    """One shot's traces d[nt][nrec], each divided by max(its l2 norm, w); a
+    trace for which that is zero stays zero."""
     d = np.asarray(d, dtype=np.float64)
-    nrm = np.sqrt(np.sum(d * d, axis=-2, keepdims=True))
-    return np.divide(d, nrm, out=np.zeros_like(d), where=nrm > 0)
+    s = np.maximum(np.sqrt(np.sum(d * d, axis=0)), w)
+    return np.divide(d, s, out=np.zeros_like(d), where=s > 0)
 
 
 def misfit_normalised(a, b):
-    """1/2 sum over traces of |a/|a| - b/|b||^2, traces along time (axis -2)."""
+    """Trace-normalised misfit of modelled traces a against observed traces b,
+    [nt][nrec] or [nshots][nt][nrec]: per shot, 1/2 sum over traces of
+    |a/max(|a|, wa) - b/max(|b|, wb)|^2, wa and wb the floors of a and b."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
     if not np.all(np.isfinite(a)):
         return math.inf
-    return misfit(normalise_traces(a), normalise_traces(b))
+    if a.ndim == 3:
+        return float(sum(misfit_normalised(a[s], b[s]) for s in range(a.shape[0])))
+    return misfit(normalise_traces(a, trace_floor(a)), normalise_traces(b, trace_floor(b)))
 
 
 def trace_misfit(prob, a, b):

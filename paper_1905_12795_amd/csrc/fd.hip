@@ -548,14 +548,35 @@ __device__ __forceinline__ void trace_sums(double *acc, int nrec, int r, float d
     gst(acc + 2 * nrec + r, gld(acc + 2 * nrec + r) + oo * oo);
 }
 
-// Misfit of one trace from its sums: 1/2 |d/|d| - o/|o||^2 with a zero trace
-// kept zero. A non-finite modelled trace gives +inf.
-__device__ __forceinline__ double trace_normalised_misfit(double dd, double dov, double oo) {
+// Misfit of one trace from its sums: 1/2 |d/sd - o/so|^2 with
+// sd = max(|d|, wd), so = max(|o|, wo) (a trace divided by zero stays zero),
+// expanded as 1/2 (|d|^2/sd^2 + |o|^2/so^2) - d.o/(sd so). A non-finite
+// modelled trace gives +inf.
+__device__ __forceinline__ double trace_normalised_misfit(double dd, double dov, double oo, double wd, double wo) {
     if (!(dd < INFINITY) || dov != dov) return INFINITY;
-    const bool hd = dd > 0.0, ho = oo > 0.0;
-    double m = 0.5 * ((hd ? 1.0 : 0.0) + (ho ? 1.0 : 0.0));
-    if (hd && ho) m -= dov / (sqrt(dd) * sqrt(oo));
-    return fmax(m, 0.0);                            // a sum of squares; 1 - cos may round below 0
+    const double sd = fmax(sqrt(dd), wd), so = fmax(sqrt(oo), wo);
+    double m = 0.5 * ((sd > 0.0 ? dd / (sd * sd) : 0.0) + (so > 0.0 ? oo / (so * so) : 0.0));
+    if (sd > 0.0 && so > 0.0) m -= dov / (sd * so);
+    return fmax(m, 0.0);                            // a sum of squares; the expansion may round below 0
+}
+
+// Floor of the trace normalisation of one side (modelled or observed) of a
+// shot from its sums of squares ss[nrec]: EMPSO_TRACE_FLOOR times the
+// largest trace norm. All threads of the block take part and receive it.
+__device__ double trace_floor(const double *ss, int nrec) {
+    __shared__ double red[256];
+    double m = 0.0;
+    for (int r = threadIdx.x; r < nrec; r += blockDim.x) m = fmax(m, ss[r]);
+    __syncthreads();
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + k]);
+        __syncthreads();
+    }
+    const double w = EMPSO_TRACE_FLOOR * sqrt(red[0]);
+    __syncthreads();
+    return w;
 }
 
 // Accumulate (or record) the receiver samples held by one lane: u4 are the
@@ -825,9 +846,13 @@ __global__ __launch_bounds__(256) void k_fitness(const RunDesc *__restrict__ run
     double s = 0.0;
     for (int run = prun[p]; run < prun[p + 1]; ++run) {
         const RunDesc &R = runs[run];
-        for (int r = threadIdx.x; r < R.nrec; r += blockDim.x)
-            s += R.norm ? trace_normalised_misfit(R.acc[r], R.acc[R.nrec + r], R.acc[2 * R.nrec + r])
-                        : 0.5 * R.acc[r];
+        if (R.norm) {
+            const double wd = trace_floor(R.acc, R.nrec), wo = trace_floor(R.acc + 2 * R.nrec, R.nrec);
+            for (int r = threadIdx.x; r < R.nrec; r += blockDim.x)
+                s += trace_normalised_misfit(R.acc[r], R.acc[R.nrec + r], R.acc[2 * R.nrec + r], wd, wo);
+        } else {
+            for (int r = threadIdx.x; r < R.nrec; r += blockDim.x) s += 0.5 * R.acc[r];
+        }
     }
     __shared__ double red[256];
     red[threadIdx.x] = s;
@@ -1252,10 +1277,12 @@ extern "C" int empso_misfit(const float *a_d, const float *b_d, int64_t n, float
     return EMPSO_OK;
 }
 
-// Misfit of each recorded trace (shot blockIdx.y, receiver r): FP64 sums
-// over time in order, as the fitness kernels accumulate them.
-__global__ __launch_bounds__(256) void k_trace_misfit(const float *__restrict__ d, const float *__restrict__ o,
-                                                      int nt, int nrec, int norm, double *__restrict__ per) {
+// Sums over time (in order, as the fitness kernels accumulate them) of each
+// recorded trace (shot blockIdx.y, receiver r) into sums[shot][k][nrec]:
+// l2: k = 0 the squared residuals; trace-normalised: k = 0, 1, 2 the sums of
+// d^2, d o and o^2.
+__global__ __launch_bounds__(256) void k_trace_sums(const float *__restrict__ d, const float *__restrict__ o,
+                                                    int nt, int nrec, int norm, double *__restrict__ sums) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= nrec) return;
     const size_t base = (size_t)blockIdx.y * nt * nrec + r;
@@ -1271,7 +1298,20 @@ __global__ __launch_bounds__(256) void k_trace_misfit(const float *__restrict__ 
             a += (double)res * (double)res;
         }
     }
-    per[(size_t)blockIdx.y * nrec + r] = norm ? trace_normalised_misfit(a, b, c) : 0.5 * a;
+    double *q = sums + (size_t)blockIdx.y * 3 * nrec + r;
+    q[0] = a;
+    q[nrec] = b;
+    q[2 * nrec] = c;
+}
+
+// Misfit of each trace of shot blockIdx.x from its sums into per[shot][nrec].
+__global__ __launch_bounds__(256) void k_trace_misfit(const double *__restrict__ sums, int nrec, int norm,
+                                                      double *__restrict__ per) {
+    const double *q = sums + (size_t)blockIdx.x * 3 * nrec;
+    const double wd = norm ? trace_floor(q, nrec) : 0.0, wo = norm ? trace_floor(q + 2 * nrec, nrec) : 0.0;
+    for (int r = threadIdx.x; r < nrec; r += blockDim.x)
+        per[(size_t)blockIdx.x * nrec + r] =
+            norm ? trace_normalised_misfit(q[r], q[nrec + r], q[2 * nrec + r], wd, wo) : 0.5 * q[r];
 }
 
 // out = sum of n values in a fixed order; not finite -> +inf.
@@ -1290,7 +1330,7 @@ __global__ __launch_bounds__(256) void k_sum_final(const double *__restrict__ v,
 
 extern "C" size_t empso_traces_misfit_workspace_bytes(const empso_problem *p, int32_t nsh) {
     if (!p || nsh < 0) return 0;
-    return align_up(sizeof(double) * (size_t)std::max(nsh, 1) * p->g.nrec, 256);
+    return align_up(sizeof(double) * 4 * (size_t)std::max(nsh, 1) * p->g.nrec, 256);
 }
 
 extern "C" int empso_traces_misfit(const empso_problem *p, const float *traces_d, const float *obs_d, int32_t nsh,
@@ -1300,11 +1340,14 @@ extern "C" int empso_traces_misfit(const empso_problem *p, const float *traces_d
     if (nsh < 0) EMPSO_FAIL(EMPSO_EINVAL, "nsh must be >= 0");
     if (ws_bytes < empso_traces_misfit_workspace_bytes(p, nsh)) EMPSO_FAIL(EMPSO_EWORKSPACE, "workspace too small");
     hipStream_t st = (hipStream_t)stream;
-    double *per = reinterpret_cast<double *>(ws);
     const int nrec = p->g.nrec;
-    if (nsh > 0)
-        k_trace_misfit<<<dim3((nrec + 255) / 256, nsh), 256, 0, st>>>(
-            traces_d, obs_d, p->g.nt, nrec, p->g.misfit == EMPSO_MISFIT_TRACE_NORMALISED ? 1 : 0, per);
+    double *sums = reinterpret_cast<double *>(ws);                 // [nsh][3][nrec]
+    double *per = sums + (size_t)3 * nsh * nrec;                   // [nsh][nrec]
+    const int norm = p->g.misfit == EMPSO_MISFIT_TRACE_NORMALISED ? 1 : 0;
+    if (nsh > 0) {
+        k_trace_sums<<<dim3((nrec + 255) / 256, nsh), 256, 0, st>>>(traces_d, obs_d, p->g.nt, nrec, norm, sums);
+        k_trace_misfit<<<nsh, 256, 0, st>>>(sums, nrec, norm, per);
+    }
     k_sum_final<<<1, 256, 0, st>>>(per, (int64_t)nsh * nrec, out_d);
     EMPSO_HIP(hipGetLastError());
     return EMPSO_OK;
@@ -1622,8 +1665,9 @@ struct GradRun {
     float *fields;              // the run's fields, gfs floats apart
     const float *obs;           // [nt][nrec]
     double *acc;                // [nrec] sum of squared residuals over k >= 1 (l2)
-    double *tsum;               // trace-normalised: [3][nrec] sums of d^2, d o, o^2; else NULL
-    float *ab;                  // trace-normalised: [2][nrec] adjoint-source weights alpha, beta
+    double *tsum;               // trace-normalised: [3][nrec] sums of d^2, d o, o^2, then the
+                                // shot's floors wd, wo; else NULL
+    float *ab;                  // trace-normalised: [3][nrec] adjoint-source factors a, b, 1/sd
     int srcS, srcC;             // stored row and column of the source
 };
 
@@ -1658,7 +1702,7 @@ static int grad_interval(const empso_problem *p, int K) {
 // s = fsrc at the source point; with tsample set, the receivers add u^{k+1}^2
 // and u^{k+1} d^{k+1} to the trace sums. Adjoint (ADJ = true): s is the
 // derivative of the misfit with respect to u^k at the receivers, u^k - d^k
-// (l2, accumulated into the misfit) or alpha u^k - beta d^k (trace-normalised),
+// (l2, accumulated into the misfit) or (a u^k - b d^k) / sd (trace-normalised),
 // and the gradient accumulator takes
 // out * [(1+a)(u^k - u^{k-1}) - (1-a)(u^{k-1} - u^{k-2})].
 // Thread (x, y) of block (bx, by, run) updates columns 4 (64 bx + x) .. +3 of
@@ -1727,7 +1771,7 @@ __global__ __launch_bounds__(256) void k_gstep(const GradRun *__restrict__ runs,
             if (r >= 0) {
                 const float ob = R.obs[(size_t)k * sh.nrec + r];
                 if (R.ab) {
-                    res[q] = fmaf(R.ab[r], ukv[q], -R.ab[sh.nrec + r] * ob);
+                    res[q] = fmaf(R.ab[r], ukv[q], -R.ab[sh.nrec + r] * ob) * R.ab[2 * sh.nrec + r];
                 } else {
                     res[q] = ukv[q] - ob;
                     R.acc[r] += (double)res[q] * (double)res[q];
@@ -1808,23 +1852,66 @@ __global__ __launch_bounds__(256) void k_gobs2(const GradRun *__restrict__ runs,
     }
 }
 
-// Adjoint-source weights of the trace-normalised misfit m = 1/2 |d/|d| - o/|o||^2:
-// dm/dd = alpha d - beta o with c = d.o / (|d| |o|), alpha = c / |d|^2,
-// beta = 1 / (|d| |o|); both zero when either trace is zero (m is then
-// constant in d, or not differentiable at d = 0).
+// Adjoint source of the trace-normalised misfit, the sum over traces of
+// m_r = 1/2 |d_r/sd_r - o_r/so_r|^2, sd_r = max(|d_r|, wd), so_r = max(|o_r|, wo),
+// wd = EMPSO_TRACE_FLOOR |d_k| (k the largest modelled trace, lowest index
+// on ties): dm/dd_r = (a_r d_r - b_r o_r) / sd_r with b_r = 1/so_r and
+//   a_r = d_r.o_r / (|d_r|^2 so_r) above the floor (|d_r| > wd: d/|d| has the
+//         Jacobian (I - e e^T)/|d|),
+//   a_r = 1/wd at or below it (sd_r = wd),
+// plus, for trace k, the dependence of wd on d_k: a_k += EMPSO_TRACE_FLOOR S
+// with S = sum over the traces at or below the floor of
+// dm_r/dwd = -(|d_r|^2/wd - d_r.o_r/so_r) / wd^2 (a fixed-order block sum).
+// Zero when sd_r or so_r is zero. Kept as the three factors a, b, 1/sd, each
+// of the size of 1/amplitude, so none overflows for data of any scale.
 __global__ __launch_bounds__(256) void k_gab(const GradRun *__restrict__ runs, int nrec) {
     const GradRun R = runs[blockIdx.x];
+    const double *dd = R.tsum, *dov = R.tsum + nrec, *oo = R.tsum + 2 * nrec;
+    const double wd = trace_floor(dd, nrec), wo = trace_floor(oo, nrec);
+    // largest modelled trace (lowest index on ties) and S
+    __shared__ double rv[256], rs[256];
+    __shared__ int ri[256];
+    double bv = -1.0, sum = 0.0;
+    int bi = nrec;
     for (int r = threadIdx.x; r < nrec; r += blockDim.x) {
-        const double dd = R.tsum[r], dov = R.tsum[nrec + r], oo = R.tsum[2 * nrec + r];
-        float al = 0.0f, be = 0.0f;
-        if (dd > 0.0 && oo > 0.0 && dd < INFINITY) {
-            const double dn = sqrt(dd), on = sqrt(oo);
-            const double c = dov / (dn * on);
-            al = (float)(c / dd);
-            be = (float)(1.0 / (dn * on));
+        if (dd[r] > bv) { bv = dd[r]; bi = r; }
+        const double so = fmax(sqrt(oo[r]), wo);
+        if (wd > 0.0 && sqrt(dd[r]) <= wd) sum -= (dd[r] / wd - (so > 0.0 ? dov[r] / so : 0.0)) / (wd * wd);
+    }
+    rv[threadIdx.x] = bv;
+    ri[threadIdx.x] = bi;
+    rs[threadIdx.x] = sum;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) {
+            const int o = threadIdx.x + k;
+            if (rv[o] > rv[threadIdx.x] || (rv[o] == rv[threadIdx.x] && ri[o] < ri[threadIdx.x])) {
+                rv[threadIdx.x] = rv[o];
+                ri[threadIdx.x] = ri[o];
+            }
+            rs[threadIdx.x] += rs[o];
         }
-        R.ab[r] = al;
-        R.ab[nrec + r] = be;
+        __syncthreads();
+    }
+    const int kmax = ri[0];
+    const double S = rs[0];
+    if (threadIdx.x == 0) {
+        R.tsum[3 * nrec] = wd;
+        R.tsum[3 * nrec + 1] = wo;
+    }
+    for (int r = threadIdx.x; r < nrec; r += blockDim.x) {
+        const double dn = sqrt(dd[r]), sd = fmax(dn, wd), so = fmax(sqrt(oo[r]), wo);
+        float a = 0.0f, b = 0.0f, isd = 0.0f;
+        if (sd > 0.0 && so > 0.0 && dd[r] < INFINITY) {
+            double ad = dn > wd ? dov[r] / (dd[r] * so) : 1.0 / wd;
+            if (r == kmax && wd > 0.0) ad += EMPSO_TRACE_FLOOR * S;
+            a = (float)ad;
+            b = (float)(1.0 / so);
+            isd = (float)(1.0 / sd);
+        }
+        R.ab[r] = a;
+        R.ab[nrec + r] = b;
+        R.ab[2 * nrec + r] = isd;
     }
 }
 
@@ -1837,7 +1924,7 @@ __global__ __launch_bounds__(256) void k_gmisfit(const GradRun *__restrict__ run
         for (int q = threadIdx.x; q < nrec; q += blockDim.x) {
             if (norm) {
                 const double *t = runs[r].tsum;
-                s += trace_normalised_misfit(t[q], t[nrec + q], t[2 * nrec + q]);
+                s += trace_normalised_misfit(t[q], t[nrec + q], t[2 * nrec + q], t[3 * nrec], t[3 * nrec + 1]);
             } else {
                 const double d0 = runs[r].obs[q];
                 s += 0.5 * (runs[r].acc[q] + d0 * d0);
@@ -1870,8 +1957,8 @@ static GradLayout grad_layout(const empso_problem *p, int K) {
     L.cd_off = take(sizeof(CoefDesc));
     L.acc_off = take(sizeof(double) * (size_t)ns * p->g.nrec);
     const bool norm = p->g.misfit == EMPSO_MISFIT_TRACE_NORMALISED;
-    L.tsum_off = take(norm ? sizeof(double) * 3 * (size_t)ns * p->g.nrec : 0);
-    L.ab_off = take(norm ? sizeof(float) * 2 * (size_t)ns * p->g.nrec : 0);
+    L.tsum_off = take(norm ? sizeof(double) * (3 * (size_t)p->g.nrec + 2) * ns : 0);
+    L.ab_off = take(norm ? sizeof(float) * 3 * (size_t)ns * p->g.nrec : 0);
     L.C_off = take(L.fb);
     L.fields_off = take(L.fb * (size_t)L.sl.total() * ns);
     L.total = k;
@@ -1913,8 +2000,8 @@ extern "C" int empso_gradient(const empso_problem *p, const float *vp_d, const f
         hr[s].fields = reinterpret_cast<float *>(w + L.fields_off + L.fb * (size_t)sl.total() * s);
         hr[s].obs = obs_d + (size_t)s * nt * p->g.nrec;
         hr[s].acc = reinterpret_cast<double *>(w + L.acc_off) + (size_t)s * p->g.nrec;
-        hr[s].tsum = norm ? reinterpret_cast<double *>(w + L.tsum_off) + (size_t)3 * s * p->g.nrec : nullptr;
-        hr[s].ab = norm ? reinterpret_cast<float *>(w + L.ab_off) + (size_t)2 * s * p->g.nrec : nullptr;
+        hr[s].tsum = norm ? reinterpret_cast<double *>(w + L.tsum_off) + (3 * (size_t)p->g.nrec + 2) * s : nullptr;
+        hr[s].ab = norm ? reinterpret_cast<float *>(w + L.ab_off) + (size_t)3 * s * p->g.nrec : nullptr;
         hr[s].srcS = p->srcI[s] + kRing;
         hr[s].srcC = p->srcJ[s] + kRing;
     }

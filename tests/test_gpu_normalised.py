@@ -208,3 +208,46 @@ def test_traces_misfit_of_forward_traces_equals_fitness(gfd):
     f = float(gfd.FitnessBatch([gp], [obs], [0])(X)[0])
     m = float(gfd.traces_misfit(gp, gfd.forward_shots(gp, vpt), obs))
     assert m == pytest.approx(f, rel=1e-6)
+
+
+def test_traces_without_arrivals_fitness_and_gradient_match_oracle(gfd):
+    """A record too short for the far receivers: their traces hold only the
+    scheme's precursor (far below the floor). Fitness and gradient match the
+    oracle, the gradient is finite, and neither depends on the scale of the
+    observed data (1e-12 .. 1e12)."""
+    g = dict(_geom(), tmax=0.3)
+    op = ofd.Problem(g)
+    gp = gfd.Problem(g, dt=op.dt, nt=op.nt)
+    vp, truth = _models(op.nz, op.nx, op.dz, op.dx)
+    d = ofd.forward_shots(op, truth)
+    peak = np.abs(d).max(axis=1)
+    assert np.sum(peak < 1e-12 * peak.max()) >= 10, "the geometry must have receivers without arrivals"
+    dobs = (d * np.asarray(SCALE)[:, None, None]).astype(np.float32)
+    ntr = op.nshots * op.nrec
+    rng = np.random.default_rng(27)
+    X = rng.uniform(1500, 2600, (3, 12))
+    fo, _ = ofd.fitness_batch(op, X.astype(np.float32).astype(np.float64), dobs)
+    obs = torch.tensor(dobs, device="cuda")
+    fb = gfd.FitnessBatch([gp], [obs], [0] * 3)
+    fg = fb(X).cpu()
+    tu = gfd.default_tuning()
+    tu.bz, tu.tsteps = 40, 2
+    assert torch.equal(fb(X, tuning=tu).cpu(), fg)
+    _say("no-arrival geometry fitness", fg.numpy(), fo)
+    for k in range(3):
+        assert _fit_close(float(fg[k]), fo[k], ntr), (k, float(fg[k]), fo[k])
+    Jo, go = ofd.gradient(op, vp.astype(np.float32).astype(np.float64), dobs)
+    vpt = torch.tensor(vp, dtype=torch.float32, device="cuda")
+    mis, grad = gfd.gradient(gp, vpt, obs)
+    assert bool(torch.isfinite(grad).all())
+    e = float(np.linalg.norm(grad.cpu().numpy() - go) / np.linalg.norm(go))
+    _say("no-arrival geometry gradient rel L2", e, "misfit", float(mis), Jo)
+    assert e <= REL_G
+    assert float(mis) == pytest.approx(Jo, rel=REL)
+    for s in (1e-12, 1e12):
+        ms, gs = gfd.gradient(gp, vpt, obs * s)
+        fs = gfd.FitnessBatch([gp], [obs * s], [0] * 3)(X).cpu()
+        assert bool(torch.isfinite(gs).all()), s
+        assert float(ms) == pytest.approx(float(mis), rel=1e-5), s
+        assert torch.allclose(fs, fg, rtol=1e-5), s
+        assert float(torch.linalg.norm(gs - grad) / torch.linalg.norm(grad)) <= 1e-4, s

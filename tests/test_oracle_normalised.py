@@ -1,8 +1,10 @@
 """Pins of the oracle's trace-normalised misfit and of its gradient.
 
 Each trace (one receiver of one shot over time) of the modelled and of the
-observed data is divided by its own l2 norm before the l2 misfit; a zero trace
-stays zero. Pinned by a hand-worked example, the cosine identity
+observed data is divided by its own l2 norm, or by the floor w = 1e-4 times
+the largest trace norm of the same shot and side where that is larger, before
+the l2 misfit; a zero trace stays zero. Pinned by hand-worked examples (above and
+below the floor), the cosine identity
 1/2 |a/|a| - b/|b||^2 = 1 - cos(a, b), the special cases (parallel,
 antiparallel, orthogonal, zero traces), invariance under a positive scale of
 any single trace, finite differences of the misfit with respect to the traces
@@ -28,6 +30,17 @@ def test_worked_example():
     d2 = np.array([[3.0, 0.0], [4.0, 2.0]])
     o2 = np.array([[1.0, 5.0], [0.0, 5.0]])
     assert fd.misfit_normalised(d2, o2) == pytest.approx(0.4 + 1.0 - 2 ** -0.5, abs=1e-15)
+
+
+def test_worked_example_below_the_floor():
+    # observed norms 10 and 5e-4 -> wo = 1e-3: o_hat = (1, 0) and (0, 5e-4)/1e-3 = (0, 0.5);
+    # modelled norms 5 and 2e-4 -> wd = 5e-4: (3, 4) -> (0.6, 0.8), (0, 2e-4)/5e-4 = (0, 0.4);
+    # 1/2 ((0.6 - 1)^2 + 0.8^2) + 1/2 (0.4 - 0.5)^2 = 0.4 + 0.005
+    o = np.array([[10.0, 0.0], [0.0, 5e-4]])
+    d = np.array([[3.0, 0.0], [4.0, 2e-4]])
+    assert fd.trace_floor(o) == pytest.approx(1e-3, rel=1e-15)
+    assert fd.trace_floor(d) == pytest.approx(5e-4, rel=1e-15)
+    assert fd.misfit_normalised(d, o) == pytest.approx(0.405, abs=1e-14)
 
 
 def test_cosine_identity_on_random_traces():
@@ -61,9 +74,11 @@ def test_invariant_under_a_scale_of_any_trace():
     a = rng.standard_normal((3, 60, 5))                                            # [shot][nt][nrec]
     b = rng.standard_normal((3, 60, 5))
     m = fd.misfit_normalised(a, b)
-    sa = rng.uniform(0.01, 100.0, size=(3, 1, 5))
-    sb = rng.uniform(0.01, 100.0, size=(3, 1, 5))
+    sa = rng.uniform(0.1, 10.0, size=(3, 1, 5))                                   # all stay above the floor
+    sb = rng.uniform(0.1, 10.0, size=(3, 1, 5))
     assert fd.misfit_normalised(a * sa, b * sb) == pytest.approx(m, rel=1e-12)
+    # and under a scale of all traces of one side, far beyond the floor's ratio
+    assert fd.misfit_normalised(a * 1e-12, b * 1e9) == pytest.approx(m, rel=1e-12)
     # a scale along time (the other axis) does change it
     st = rng.uniform(0.5, 2.0, size=(1, 60, 1))
     assert abs(fd.misfit_normalised(a * st, b) - m) > 1e-3 * m
@@ -74,9 +89,13 @@ def test_adjoint_data_is_the_derivative_of_the_misfit():
     d = rng.standard_normal((30, 4))
     o = rng.standard_normal((30, 4))
     o[:, 2] = 0.0                                                                  # a zero observed trace
+    d[:, 1] *= 1e-6                                                                # a modelled trace below the floor
+    d[:, 3] *= 3.0                                                                 # the largest modelled trace
+    assert np.linalg.norm(d[:, 1]) < fd.trace_floor(d)
+    assert int(np.argmax(np.linalg.norm(d, axis=0))) == 3
     g = d - fd.normalised_adjoint_data(d, o)
     h = 1e-6
-    for (n, r) in [(0, 0), (7, 1), (29, 3), (12, 2)]:
+    for (n, r) in [(0, 0), (7, 1), (29, 3), (5, 3), (12, 2), (3, 1)]:
         e = np.zeros_like(d)
         e[n, r] = h
         num = (fd.misfit_normalised(d + e, o) - fd.misfit_normalised(d - e, o)) / (2 * h)
@@ -151,9 +170,9 @@ def test_pointwise_derivative_matches_central_differences(setup, ij):
 
 # ---- planted mistakes --------------------------------------------------------
 
-def _normalise_over_receivers(d):
+def _normalise_over_receivers(d, w):
     d = np.asarray(d, dtype=np.float64)
-    nrm = np.sqrt(np.sum(d * d, axis=-1, keepdims=True))
+    nrm = np.maximum(np.sqrt(np.sum(d * d, axis=-1, keepdims=True)), w)
     return np.divide(d, nrm, out=np.zeros_like(d), where=nrm > 0)
 
 
@@ -163,15 +182,50 @@ def test_planted_normalisation_axis_mistake_is_caught(monkeypatch):
         test_invariant_under_a_scale_of_any_trace()
 
 
-def test_planted_missing_cosine_factor_is_caught(monkeypatch):
+def test_planted_missing_projection_is_caught(monkeypatch):
     def bad(d, o):
-        d = np.asarray(d, dtype=np.float64)
-        o = np.asarray(o, dtype=np.float64)
-        dn = np.sqrt(np.sum(d * d, axis=0))
-        on = np.sqrt(np.sum(o * o, axis=0))
-        ok = (dn > 0) & (on > 0)
-        dns, ons = np.where(ok, dn, 1.0), np.where(ok, on, 1.0)
-        return d - np.where(ok, d / dns ** 2 - o / (dns * ons), 0.0)            # c dropped
+        oh = fd.normalise_traces(o, fd.trace_floor(o))
+        n = np.maximum(np.sqrt(np.sum(d * d, axis=0)), fd.trace_floor(d))
+        return d - (d / n - oh) / n                                               # (I - e e^T) dropped
     monkeypatch.setattr(fd, "normalised_adjoint_data", bad)
     with pytest.raises(AssertionError):
         test_adjoint_data_is_the_derivative_of_the_misfit()
+
+
+def test_planted_missing_floor_derivative_is_caught(monkeypatch):
+    real = fd.normalised_adjoint_data
+
+    def bad(d, o):
+        out = real(d, o)
+        # undo the floor term: recompute trace k's derivative without it
+        w = fd.trace_floor(d)
+        oh = fd.normalise_traces(o, fd.trace_floor(o))
+        k = int(np.argmax(np.linalg.norm(d, axis=0)))
+        x, y = d[:, k], oh[:, k]
+        n = np.linalg.norm(x)
+        e = x / n
+        out[:, k] = x - ((e - y) - e * np.dot(e, e - y)) / n
+        return out
+    monkeypatch.setattr(fd, "normalised_adjoint_data", bad)
+    with pytest.raises(AssertionError):
+        test_adjoint_data_is_the_derivative_of_the_misfit()
+
+
+def test_planted_missing_floor_is_caught(monkeypatch):
+    monkeypatch.setattr(fd, "TRACE_FLOOR", 0.0)
+    with pytest.raises(AssertionError):
+        test_worked_example_below_the_floor()
+
+
+def test_planted_shared_floor_is_caught(monkeypatch):
+    """A floor taken from the observed side for both sides breaks the scale invariance."""
+    def bad(a, b):
+        a = np.asarray(a, dtype=np.float64)
+        b = np.asarray(b, dtype=np.float64)
+        if a.ndim == 3:
+            return float(sum(bad(a[s], b[s]) for s in range(a.shape[0])))
+        w = fd.trace_floor(b)
+        return fd.misfit(fd.normalise_traces(a, w), fd.normalise_traces(b, w))
+    monkeypatch.setattr(fd, "misfit_normalised", bad)
+    with pytest.raises(AssertionError):
+        test_invariant_under_a_scale_of_any_trace()
