@@ -159,6 +159,33 @@ def gradient_timing(workload, reps, modes=(False, True)):
                "misfit": float(out[0])})
 
 
+def bandwidth(mib, reps):
+    """Achievable HBM rates of plain streaming operations on a buffer of `mib`
+    MiB (context for the stencils' rooflines): device-to-device copy (read +
+    write), an elementwise add of a scalar (read + write), fill (write) and
+    sum (read). Median of `reps` timings with events on the current stream."""
+    n = mib * (1 << 20) // 4
+    a = torch.rand(n, device="cuda")
+    b = torch.empty_like(a)
+    ops = {"copy": (lambda: b.copy_(a), 8), "add_scalar": (lambda: torch.add(a, 1.0, out=b), 8),
+           "fill": (lambda: b.fill_(1.0), 4), "sum": (lambda: a.sum(), 4)}
+    out = {"bytes_per_element": {k: v[1] for k, v in ops.items()}, "mib": mib}
+    for name, (fn, bpe) in ops.items():
+        fn()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1) * 1e-3)
+        t = float(np.median(ts))
+        out[name + "_GBps"] = bpe * n / t / 1e9
+        out[name + "_us"] = t * 1e6
+    _emit(out)
+
+
 def mlp_timing(reps):
     """Surrogate network at the surrogate workload's shape (D = 60, H = 256):
     inference on 1024 candidates and training steps of 256 rows."""
@@ -211,6 +238,9 @@ def main():
     gr.add_argument("--workload", default="realistic", choices=["tiny", "realistic", "irregular", "crime_free", "full"])
     gr.add_argument("--reps", type=int, default=2)
     gr.add_argument("--plain-only", action="store_true", help="skip the run that also returns the illumination")
+    bw = sub.add_parser("bandwidth")
+    bw.add_argument("--mib", type=int, default=1024)
+    bw.add_argument("--reps", type=int, default=20)
     ml = sub.add_parser("mlp")
     ml.add_argument("--reps", type=int, default=50)
     a = ap.parse_args()
@@ -220,6 +250,8 @@ def main():
         gradient_timing(a.workload, a.reps, (False,) if a.plain_only else (False, True))
     elif a.cmd == "mlp":
         mlp_timing(a.reps)
+    elif a.cmd == "bandwidth":
+        bandwidth(a.mib, a.reps)
     elif a.cmd == "fwi":
         local_fwi(a.workload, a.search_iters, a.fwi_iters, a.seed, a.misfit)
     else:
