@@ -251,3 +251,53 @@ def test_traces_without_arrivals_fitness_and_gradient_match_oracle(gfd):
         assert float(ms) == pytest.approx(float(mis), rel=1e-5), s
         assert torch.allclose(fs, fg, rtol=1e-5), s
         assert float(torch.linalg.norm(gs - grad) / torch.linalg.norm(grad)) <= 1e-4, s
+
+
+@pytest.mark.timeout(600)
+def test_crime_free_full_size_directional_derivative(gfd):
+    """The normalised gradient at full size on the crime-free data (16 shots,
+    nt = 8114, far receivers below the floor in a linear 1.5-5.5 km/s model)
+    against central differences of the GPU misfit along a smooth direction.
+    The normalised misfit bends more than the l2 one over the steps used
+    here, so the central differences at 10 and 20 m/s are combined by
+    Richardson extrapolation (the step-squared error cancels); bar 5e-3."""
+    from paper_1905_12795_amd import search
+    from workloads.configs import true_model
+    g = dict(config("crime_free"), misfit="trace_normalised")
+    gp = gfd.Problem(g)
+    obs = search.observed_for(g, gp, true_model(g))
+    z = np.arange(g["nz"])[:, None] * g["dz"]
+    x = np.arange(g["nx"])[None, :] * g["dx"]
+    vpt = torch.tensor(1500.0 + 4000.0 * z / z.max() + 0 * x, dtype=torch.float32, device="cuda")
+    mis, grad = gfd.gradient(gp, vpt, obs)
+    assert bool(torch.isfinite(grad).all())
+    from paper_1905_12795_amd import fwi
+    d = torch.tensor(np.sin(z / 400.0) * np.cos(x / 900.0), dtype=torch.float32, device="cuda")
+
+    def central(eps):
+        return (fwi.model_misfit(gp, vpt + eps * d, obs) - fwi.model_misfit(gp, vpt - eps * d, obs)) / (2 * eps)
+
+    c10, c20 = central(10.0), central(20.0)
+    rich = (4.0 * c10 - c20) / 3.0
+    dot = float(torch.sum(grad.double() * d.double()))
+    _say("normalised directional derivative: adjoint %.6g; central differences %.6g (10 m/s), %.6g (20 m/s), "
+         "extrapolated %.6g (misfit %.6g)" % (dot, c10, c20, rich, float(mis)))
+    assert dot == pytest.approx(rich, rel=5e-3)
+
+
+def test_local_fwi_with_the_normalised_misfit(gfd):
+    """Data of unknown amplitude (a factor per shot): the local FWI with the
+    trace-normalised misfit lowers the misfit monotonically and the model error."""
+    from paper_1905_12795_amd import fwi
+    g = _geom()
+    gp = gfd.Problem(g)
+    vp, truth = _models(g["nz"], g["nx"], g["dz"], g["dx"])
+    obs = gfd.forward_shots(gp, torch.tensor(truth, dtype=torch.float32, device="cuda"))
+    obs = obs * torch.tensor(SCALE, device="cuda")[:, None, None]
+    v, hist = fwi.invert(gp, obs, vp, 8)
+    J = [h["misfit"] for h in hist]
+    _say("normalised local FWI misfits", J, "rms model error", fwi.rms_error(vp, truth), "->",
+         fwi.rms_error(v, truth))
+    assert all(b <= a for a, b in zip(J, J[1:]))
+    assert J[-1] < 0.5 * J[0]
+    assert fwi.rms_error(v, truth) < fwi.rms_error(vp, truth)
