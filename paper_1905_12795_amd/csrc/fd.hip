@@ -916,10 +916,28 @@ static const int kTailBz = 40;     // tile height of the single-step launches th
 
 static int out_cols(int T) { return kTileX - 8 * T; }
 
+// Height of the z-strips of a grid for tile height bz and depth T: about bz
+// rows, balanced over the grid, rounded up so that a strip's march (its
+// 8(T-1) queue-fill steps plus its rows) is a whole number of 10-step
+// blocks; the last strip takes the rest. Never below ceil(Nz / ceil(Nz/bz)),
+// so a grid has at most ceil(Nz/bz) strips.
+static int strip_height(const empso_problem *p, int bz, int T) {
+    const int nstrips = (p->Nz + bz - 1) / bz;
+    const int fill = 8 * (T - 1);
+    return ((p->Nz + nstrips - 1) / nstrips + fill + kQueue - 1) / kQueue * kQueue - fill;
+}
+
 static int tiles_of(const empso_problem *p, int bz, int T) {
-    const int zt = (p->Nz + bz - 1) / bz;
+    const int h = strip_height(p, bz, T);
+    const int zt = (p->Nz + h - 1) / h;
     const int xt = (p->Nx + out_cols(T) - 1) / out_cols(T);
     return zt * xt;
+}
+
+// Upper bound of tiles_of over every valid tuning (bz >= kMinBz, T <= kMaxT):
+// sizes the tile tables.
+static int tile_capacity(const empso_problem *p) {
+    return ((p->Nz + kMinBz - 1) / kMinBz) * ((p->Nx + out_cols(kMaxT) - 1) / out_cols(kMaxT));
 }
 
 // stored rows of a field: ring, padded grid, ring
@@ -949,7 +967,7 @@ static Layout make_layout(const std::vector<const empso_problem *> &pp, const st
     L.iso = true;
     for (const RunSpec &r : runs) {
         L.iso = L.iso && (r.p->g.dz == r.p->g.dx);
-        cap += tiles_of(r.p, kMinBz, kMaxT);
+        cap += tile_capacity(r.p);
         L.ntiles += tiles_of(r.p, bz, T);
         L.ntiles1 += tiles_of(r.p, kTailBz, 1);
     }
@@ -1075,10 +1093,7 @@ static void fill_tiles(int4 *td, const std::vector<const empso_problem *> &pp, c
         const empso_problem *p = pp[q];
         size_t r1 = r0;
         while (r1 < runs.size() && runs[r1].particle == (int)q) ++r1;
-        // z-strips of about bz rows, balanced over the grid (heights rounded
-        // up to the march's 10-step blocks, the last strip takes the rest)
-        const int nstrips = (p->Nz + bz - 1) / bz;
-        const int h = ((p->Nz + nstrips - 1) / nstrips + kQueue - 1) / kQueue * kQueue;
+        const int h = strip_height(p, bz, T);
         const int zt = (p->Nz + h - 1) / h, xt = (p->Nx + W - 1) / W;
         for (int zs = 0; zs < zt; ++zs)
             for (int xs = 0; xs < xt; ++xs)
