@@ -63,6 +63,30 @@ def measured_traffic(per_launch_updates, tu):
     return d.get("hbm_bytes_per_launch")
 
 
+# VALU issue capacity of the GPU: 256 compute units x 4 SIMDs, each issuing
+# one wave64 FP32 vector instruction per 4 cycles (16 lanes), at 2.4 GHz.
+SIMDS = 256 * 4
+CLOCK_HZ = 2.4e9
+CYCLES_PER_VALU = 4
+
+
+def measured_valu(per_launch_updates, tu):
+    """Wave-level VALU instructions per stencil launch (SQ_INSTS_VALU) from the
+    committed counter summary, if it was taken on the current kernel source
+    with this tuning; else None."""
+    path = os.path.join(ROOT, "profiles", "k_tb_realistic_valu.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    if d.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    if d.get("updates_per_launch") != per_launch_updates:
+        return None
+    if d.get("tuning", {}).get("bz") != tu.bz or d.get("tuning", {}).get("tsteps") != tu.tsteps:
+        return None
+    return d.get("valu_instructions_per_launch")
+
+
 def cpu_baseline(geom, dt, nt, threads, steps):
     """Oracle throughput on the host: the forward runs of 1 particle x all shots
     over the first `steps` time steps (all of them by default: one complete
@@ -265,6 +289,7 @@ def main():
     alg = upd_per_launch * BYTES_PER_UPDATE
     achieved = alg / launch_s / 1e9
     traffic = measured_traffic(upd_per_launch, tu)
+    valu = measured_valu(upd_per_launch, tu)
     out = {
         "metric": METRIC, "value": evals_per_s, "unit": "fitness evals/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
@@ -284,7 +309,12 @@ def main():
                      "algorithmic_bytes_per_launch": alg, "updates_per_launch": upd_per_launch,
                      "bytes_per_update": BYTES_PER_UPDATE, "time_steps_per_launch": T,
                      "avg_launch_us": launch_s * 1e6, "isolated_launch_us": iso_us_step * T,
-                     "measured_frac": None if traffic is None else traffic / launch_s / 1e9 / HBM_PEAK_GBS},
+                     "measured_frac": None if traffic is None else traffic / launch_s / 1e9 / HBM_PEAK_GBS,
+                     # the kernel's binding limit: share of the VALU issue capacity its
+                     # counted instructions take over the measured launch time
+                     "valu_instructions_per_launch": valu,
+                     "valu_issue_frac": None if valu is None else
+                     valu * CYCLES_PER_VALU / (SIMDS * CLOCK_HZ * launch_s)},
     }
     if not args.no_gradient:
         out["gradient"] = gradient_report(prob, dobs)
