@@ -92,3 +92,35 @@ def test_random_geometry_matches_oracle(gfd, seed):
     n2 = float(np.sum(dobs.astype(np.float64) ** 2))
     for k in range(3):
         assert _fit_close(fg[k], fo[k], n2), (k, fg[k], fo[k], outs[0][0])
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_random_geometry_gradient_matches_oracle(gfd, seed):
+    """The misfit gradient (l2 on even seeds, trace-normalised on odd ones, the
+    observed data then scaled per shot) on random small geometries: within the
+    gradient bar (1e-3 relative L2) of the oracle's discrete adjoint, misfit
+    within 2e-4, and identical for two checkpoint intervals."""
+    g, rng = _random_geom(100 + seed)
+    if seed % 2:
+        g["misfit"] = "trace_normalised"
+    op = ofd.Problem(g)
+    gp = gfd.Problem(g, dt=op.dt, nt=op.nt)
+    ncz, ncx = g["ncz"], g["ncx"]
+    truth = ofd.vp_from_nodes(rng.uniform(1500, 2600, ncz * ncx), ncz, ncx, g["nz"], g["nx"])
+    vp = ofd.vp_from_nodes(rng.uniform(1500, 2600, ncz * ncx), ncz, ncx, g["nz"], g["nx"])
+    vp = vp.astype(np.float32).astype(np.float64)
+    dobs = ofd.forward_shots(op, truth)
+    if seed % 2:
+        dobs = dobs * rng.uniform(0.1, 10.0, (op.nshots, 1, 1))
+    dobs = dobs.astype(np.float32)
+    Jo, go = ofd.gradient(op, vp, dobs)
+    vpt = torch.tensor(vp, dtype=torch.float32, device="cuda")
+    obs = torch.tensor(dobs, device="cuda")
+    mis, grad = gfd.gradient(gp, vpt, obs)
+    e = float(np.linalg.norm(grad.cpu().numpy() - go) / np.linalg.norm(go))
+    _say("seed %d (%s): %dx%d nbl %d, %d shots, nt %d: gradient rel L2 %.3g, misfit %.6g vs %.6g"
+         % (seed, g.get("misfit", "l2"), g["nz"], g["nx"], g["nbl"], op.nshots, op.nt, e, float(mis), Jo))
+    assert e <= 1e-3
+    assert float(mis) == pytest.approx(Jo, rel=REL)
+    m2, g2 = gfd.gradient(gp, vpt, obs, checkpoint_every=int(rng.integers(1, 40)))
+    assert torch.equal(m2, mis) and torch.equal(g2, grad)
