@@ -47,20 +47,36 @@ def kernel_source_hash():
     return hashlib.sha256(src[a:a2] + src[b:c]).hexdigest()[:16]
 
 
-def measured_traffic(per_launch_updates, tu):
+def strip_rows(Nz, bz, T):
+    """Height of the z-strips the library launches for tile height bz and depth
+    T on a grid of Nz padded rows (its tiling rule: about bz rows, balanced,
+    rounded so that 8(T-1) fill steps plus the rows make whole 10-step
+    blocks). Counter summaries apply to the launched tiles, so two tunings
+    with the same depth and strips share them."""
+    n = -(-Nz // bz)
+    fill = 8 * (T - 1)
+    return -(-(-(-Nz // n) + fill) // 10) * 10 - fill
+
+
+def _counters_apply(d, per_launch_updates, tu, Nz):
+    if d.get("kernel_source_sha256_16") != kernel_source_hash():
+        return False
+    if d.get("updates_per_launch") != per_launch_updates:
+        return False
+    t = d.get("tuning", {})
+    if t.get("tsteps") != tu.tsteps or "bz" not in t:
+        return False
+    return strip_rows(Nz, t["bz"], tu.tsteps) == strip_rows(Nz, tu.bz, tu.tsteps)
+
+
+def measured_traffic(per_launch_updates, tu, Nz):
     """HBM bytes per stencil launch from the committed counter summary, if it
     was taken on the current kernel source with this tuning; else None."""
     path = os.path.join(ROOT, "profiles", "k_tb_realistic_traffic.json")
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
-    if d.get("kernel_source_sha256_16") != kernel_source_hash():
-        return None
-    if d.get("updates_per_launch") != per_launch_updates:
-        return None
-    if d.get("tuning", {}).get("bz") != tu.bz or d.get("tuning", {}).get("tsteps") != tu.tsteps:
-        return None
-    return d.get("hbm_bytes_per_launch")
+    return d.get("hbm_bytes_per_launch") if _counters_apply(d, per_launch_updates, tu, Nz) else None
 
 
 # VALU issue capacity of the GPU: 256 compute units x 4 SIMDs, each issuing
@@ -70,7 +86,7 @@ CLOCK_HZ = 2.4e9
 CYCLES_PER_VALU = 4
 
 
-def measured_valu(per_launch_updates, tu):
+def measured_valu(per_launch_updates, tu, Nz):
     """Wave-level VALU instructions per stencil launch (SQ_INSTS_VALU) from the
     committed counter summary, if it was taken on the current kernel source
     with this tuning; else None."""
@@ -78,13 +94,7 @@ def measured_valu(per_launch_updates, tu):
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
-    if d.get("kernel_source_sha256_16") != kernel_source_hash():
-        return None
-    if d.get("updates_per_launch") != per_launch_updates:
-        return None
-    if d.get("tuning", {}).get("bz") != tu.bz or d.get("tuning", {}).get("tsteps") != tu.tsteps:
-        return None
-    return d.get("valu_instructions_per_launch")
+    return d.get("valu_instructions_per_launch") if _counters_apply(d, per_launch_updates, tu, Nz) else None
 
 
 def cpu_baseline(geom, dt, nt, threads, steps):
@@ -288,8 +298,8 @@ def main():
     iso_us_step = fb.time_tuning(swarm.ask(), tu, reps=8)
     alg = upd_per_launch * BYTES_PER_UPDATE
     achieved = alg / launch_s / 1e9
-    traffic = measured_traffic(upd_per_launch, tu)
-    valu = measured_valu(upd_per_launch, tu)
+    traffic = measured_traffic(upd_per_launch, tu, prob.info.Nz)
+    valu = measured_valu(upd_per_launch, tu, prob.info.Nz)
     out = {
         "metric": METRIC, "value": evals_per_s, "unit": "fitness evals/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,

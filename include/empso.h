@@ -254,7 +254,9 @@ int empso_default_tuning(empso_tuning *out);
 
 /* Autotuner: with the same arguments as empso_fitness_batch, time a few
  * launches of the finite-difference kernel for every tile height of 20, 40,
- * 80, 160, 240 and 320 rows and temporal-blocking depth on this batch and write the fastest tuning to
+ * 80, 160, 240 and 320 rows and temporal-blocking depth on this batch (a
+ * height that gives every grid the same strips as a lower one launches the
+ * same tiles and is skipped) and write the fastest tuning to
  * *best (graph replay on) and its time per time step in microseconds to
  * *best_us_per_step (may be NULL). Every tuning gives bit-identical results.
  * Synchronises the stream; overwrites the workspace. */

@@ -1633,7 +1633,14 @@ extern "C" int empso_autotune_fitness(const empso_problem *const *probs, int32_t
     empso_default_tuning(&bt);
     std::lock_guard<std::mutex> lk(g_plan_mu);
     for (int T = 1; T <= kMaxT && rc == EMPSO_OK; ++T) {
+        std::vector<std::vector<int>> seen;    // strip heights of the tilings timed at this depth
         for (int bi = 0; bi < 6 && rc == EMPSO_OK; ++bi) {
+            // tile heights that give every grid of the batch the same strips
+            // launch the same tiles: time the first of them only
+            std::vector<int> sig;
+            for (const empso_problem *p : pp) sig.push_back(strip_height(p, bzs[bi], T));
+            if (std::find(seen.begin(), seen.end(), sig) != seen.end()) continue;
+            seen.push_back(sig);
             empso_tuning tu;
             empso_default_tuning(&tu);
             tu.bz = bzs[bi];
