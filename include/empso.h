@@ -144,7 +144,10 @@ typedef struct {
     int32_t variant;         /* reserved, 0                                             */
     int32_t bz;              /* target output rows per tile, a multiple of 20 in 20..320;
                               * each grid's rows are split into equal strips of about
-                              * this height (rounded up to multiples of 10)             */
+                              * this height, rounded up so that a strip's march (its
+                              * 8 (tsteps - 1) queue-fill steps plus its rows) is a
+                              * whole number of 10-step blocks; the last strip takes
+                              * the rest                                                */
     int32_t tsteps;          /* time steps per launch (temporal-blocking depth): 1..4   */
     int32_t prefetch;        /* rows of u requested ahead of use: 1                     */
     int32_t use_graph;       /* 1: replay the time loop from a captured HIP graph       */
