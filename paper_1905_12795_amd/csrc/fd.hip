@@ -1673,7 +1673,9 @@ extern "C" int empso_autotune_fitness(const empso_problem *const *probs, int32_t
 // r^k = u^k - d^k injected at the receivers:
 //   (1+a) psi^k = 2 psi^{k+1} - (1-a) psi^{k+2} + C (Lap_h psi^{k+1} + r^k),
 // k = nt-1 .. 1, psi^{nt} = psi^{nt+1} = 0, and
-//   dJ/dC = sum_n psi^{n+1} [(1+a) u^{n+1} - 2 u^n + (1-a) u^{n-1}] / C^2,
+//   dJ/dC = sum_n psi^{n+1} [(1+a) u^{n+1} - 2 u^n + (1-a) u^{n-1}] / C^2
+// (accumulated as the same sum rearranged by parts: u^n times psi's second
+// time difference),
 //   dJ/dv = dJ/dC 2 v dt^2, folded from the padded grid onto the physical
 // model (each padded point adds into the point it copies) and summed over
 // shots. Both directions use the increment form of the fitness kernels. The
@@ -1726,13 +1728,16 @@ static int grad_interval(const empso_problem *p, int K) {
 // derivative of the misfit with respect to u^k at the receivers, u^k - d^k
 // (l2, accumulated into the misfit) or (a u^k - b d^k) / sd (trace-normalised),
 // and the gradient accumulator takes
-// out * [(1+a)(u^k - u^{k-1}) - (1-a)(u^{k-1} - u^{k-2})].
+// u^k [(1+a)(psi^k - psi^{k+1}) - (1-a)(psi^{k+1} - psi^{k+2})]: the imaging
+// sum over k of psi^k times u's second time difference at k, rearranged by
+// parts (u^0 = u^{-1} = 0 and psi^{nt} = psi^{nt+1} = 0, so no boundary
+// terms), which needs one stored forward level per step instead of three.
 // Thread (x, y) of block (bx, by, run) updates columns 4 (64 bx + x) .. +3 of
 // padded row 4 by + y.
 template <bool ADJ, bool ISO>
 __global__ __launch_bounds__(256) void k_gstep(const GradRun *__restrict__ runs, const GradShared sh, int cur,
-                                               int prev, int out, float fsrc, int k, int uk, int uk1, int uk2,
-                                               int gacc, int illum, int tsample) {
+                                               int prev, int out, float fsrc, int k, int uk, int gacc, int illum,
+                                               int tsample) {
     const int I = blockIdx.y * 4 + (int)threadIdx.y;
     const int J0 = 4 * (blockIdx.x * 64 + (int)threadIdx.x);
     if (I >= sh.Nz || J0 >= sh.Nx) return;
@@ -1754,12 +1759,8 @@ __global__ __launch_bounds__(256) void k_gstep(const GradRun *__restrict__ runs,
     const float pv[4] = {pv4.x, pv4.y, pv4.z, pv4.w}, Cv[4] = {C4.x, C4.y, C4.z, C4.w};
     const float cz[4] = {sh.cz1, sh.cz2, sh.cz3, sh.cz4}, cx[4] = {sh.cx1, sh.cx2, sh.cx3, sh.cx4};
     const float azr = sh.az[I];
-    float4 Uk4, Uk14, Uk24;
-    if (ADJ) {
-        Uk4 = ld4(R.fields + (size_t)uk * sh.gfs, o);
-        Uk14 = ld4(R.fields + (size_t)uk1 * sh.gfs, o);
-        Uk24 = ld4(R.fields + (size_t)uk2 * sh.gfs, o);
-    }
+    float4 Uk4;
+    if (ADJ) Uk4 = ld4(R.fields + (size_t)uk * sh.gfs, o);
     const float ukv[4] = {ADJ ? Uk4.x : 0.f, ADJ ? Uk4.y : 0.f, ADJ ? Uk4.z : 0.f, ADJ ? Uk4.w : 0.f};
     float res[4];
 #pragma unroll
@@ -1815,9 +1816,9 @@ __global__ __launch_bounds__(256) void k_gstep(const GradRun *__restrict__ runs,
             }
         }
         if (ADJ) {
-            const float u0 = (&Uk4.x)[q], u1 = (&Uk14.x)[q], u2 = (&Uk24.x)[q];
+            const float u0 = (&Uk4.x)[q];
             float *g = R.fields + (size_t)gacc * sh.gfs + o + q;
-            *g = fmaf(un, (1.0f + a) * (u0 - u1) - (1.0f - a) * (u1 - u2), *g);
+            *g = fmaf(u0, (1.0f + a) * (un - u) - (1.0f - a) * (u - pv[q]), *g);
             if (illum) {
                 float *il = R.fields + (size_t)(gacc + 1) * sh.gfs + o + q;  // illumination: sum of u^k^2
                 *il = fmaf(u0, u0, *il);
@@ -2060,16 +2061,16 @@ extern "C" int empso_gradient(const empso_problem *p, const float *vp_d, const f
     auto step_fwd = [&](int n, int cur, int prev, int out, int tsample) {
         const float fs = wav[n] * p->wscale;
         if (iso)
-            k_gstep<false, true><<<grd, blk, 0, st>>>(runs, sh, cur, prev, out, fs, n, 0, 0, 0, 0, 0, tsample);
+            k_gstep<false, true><<<grd, blk, 0, st>>>(runs, sh, cur, prev, out, fs, n, 0, 0, 0, tsample);
         else
-            k_gstep<false, false><<<grd, blk, 0, st>>>(runs, sh, cur, prev, out, fs, n, 0, 0, 0, 0, 0, tsample);
+            k_gstep<false, false><<<grd, blk, 0, st>>>(runs, sh, cur, prev, out, fs, n, 0, 0, 0, tsample);
     };
-    auto step_adj = [&](int k, int cur, int prev, int out, int uk, int uk1, int uk2) {
+    auto step_adj = [&](int k, int cur, int prev, int out, int uk) {
         if (iso)
-            k_gstep<true, true><<<grd, blk, 0, st>>>(runs, sh, cur, prev, out, 0.0f, k, uk, uk1, uk2, sl.gacc(),
+            k_gstep<true, true><<<grd, blk, 0, st>>>(runs, sh, cur, prev, out, 0.0f, k, uk, sl.gacc(),
                                                      illum_d != nullptr, 0);
         else
-            k_gstep<true, false><<<grd, blk, 0, st>>>(runs, sh, cur, prev, out, 0.0f, k, uk, uk1, uk2, sl.gacc(),
+            k_gstep<true, false><<<grd, blk, 0, st>>>(runs, sh, cur, prev, out, 0.0f, k, uk, sl.gacc(),
                                                       illum_d != nullptr, 0);
     };
     auto copy = [&](int src, int dst) { k_gcopy<<<dim3(cblocks, ns), 256, 0, st>>>(runs, gfs, src, dst); };
@@ -2107,7 +2108,7 @@ extern "C" int empso_gradient(const empso_problem *p, const float *vp_d, const f
         }
         for (int n = b; n < e; ++n) step_fwd(n, sl.seg(n - b + 1), sl.seg(n - b), sl.seg(n - b + 2), 0);
         for (int k = e; k >= b + 1; --k)
-            step_adj(k, sl.adj(k + 1), sl.adj(k + 2), sl.adj(k), sl.seg(k - b + 1), sl.seg(k - b), sl.seg(k - b - 1));
+            step_adj(k, sl.adj(k + 1), sl.adj(k + 2), sl.adj(k), sl.seg(k - b + 1));
     }
     const int64_t npts = (int64_t)p->g.nz * p->g.nx;
     k_gfold<<<(int)std::min<int64_t>(2048, (npts + 255) / 256), 256, 0, st>>>(runs, ns, sh, sl.gacc(), vp_d, p->g.nz,
