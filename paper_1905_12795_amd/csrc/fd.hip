@@ -1733,12 +1733,13 @@ static int grad_interval(const empso_problem *p, int K) {
 // parts (u^0 = u^{-1} = 0 and psi^{nt} = psi^{nt+1} = 0, so no boundary
 // terms), which needs one stored forward level per step instead of three.
 // Thread (x, y) of block (bx, by, run) updates columns 4 (64 bx + x) .. +3 of
-// padded row 4 by + y.
+// padded row kGRows by + y.
+static constexpr int kGRows = 4;     // rows per block of k_gstep
 template <bool ADJ, bool ISO>
-__global__ __launch_bounds__(256) void k_gstep(const GradRun *__restrict__ runs, const GradShared sh, int cur,
+__global__ __launch_bounds__(64 * kGRows) void k_gstep(const GradRun *__restrict__ runs, const GradShared sh, int cur,
                                                int prev, int out, float fsrc, int k, int uk, int gacc, int illum,
                                                int tsample) {
-    const int I = blockIdx.y * 4 + (int)threadIdx.y;
+    const int I = blockIdx.y * kGRows + (int)threadIdx.y;
     const int J0 = 4 * (blockIdx.x * 64 + (int)threadIdx.x);
     if (I >= sh.Nz || J0 >= sh.Nx) return;
     const GradRun R = runs[blockIdx.z];
@@ -2053,7 +2054,7 @@ extern "C" int empso_gradient(const empso_problem *p, const float *vp_d, const f
     EMPSO_HIP(hipMemcpy(cdd, &cd, sizeof(CoefDesc), hipMemcpyHostToDevice));
     k_coef<<<dim3(1024, 1), 256, 0, st>>>(cdd);
 
-    const dim3 blk(64, 4), grd((p->Nx + 255) / 256, (p->Nz + 3) / 4, ns);
+    const dim3 blk(64, kGRows), grd((p->Nx + 255) / 256, (p->Nz + kGRows - 1) / kGRows, ns);
     const int cblocks = (int)std::min<size_t>(4096, (gfs / 4 + 255) / 256);
     // the source value of step n is wavelet[n] / (dz dx), read on the host
     std::vector<float> wav(nt);
