@@ -175,6 +175,10 @@ def test_l2_and_normalised_problems_in_one_process_keep_their_misfits(gfd):
     # random observed traces are nearly orthogonal to any model's: about 1 per trace
     assert np.all(np.abs(fn / (pn.nshots * pn.nrec) - 1.0) < 0.1), fn
     assert np.all(fl > 0.4 * float((obs.double() ** 2).sum()))
+    # one batch mixing both problems gives each particle its own problem's misfit, bit for bit
+    Xm = np.concatenate([X, X])
+    fm = gfd.FitnessBatch([pn, pl], [obs, obs], [0, 0, 1, 1])(Xm).cpu().numpy()
+    assert np.array_equal(fm[:2], fn) and np.array_equal(fm[2:], fl), (fm, fn, fl)
 
 
 @pytest.mark.parametrize("kind", ["l2", "trace_normalised"])
