@@ -170,3 +170,26 @@ def test_illumination_equals_trace_energy_on_an_interior_receiver_row(gfd):
     got = ill.cpu().numpy()[5, 3:28:3].astype(np.float64)
     assert np.allclose(got, want, rtol=1e-4, atol=0), (got, want)
     assert float(ill.min()) >= 0.0
+
+
+def test_multiscale_fwi_two_bands(gfd):
+    """The band-by-band schedule: a 5 Hz stage then a 10 Hz stage, each with its
+    own problem and data; the misfit falls within each band and the model
+    error ends below the starting one."""
+    from paper_1905_12795_amd import fwi
+    stages = []
+    for f0 in (5.0, 10.0):
+        g = _wide()
+        g.update(f0=f0, tmax=0.6)
+        gp = gfd.Problem(g)
+        _, truth = _models(g["nz"], g["nx"], g["dz"], g["dx"])
+        obs = gfd.forward_shots(gp, torch.tensor(truth, dtype=torch.float32, device="cuda"))
+        stages.append((gp, obs, 4))
+    vp, truth = _models(g["nz"], g["nx"], g["dz"], g["dx"])
+    v, hists = fwi.multiscale(stages, vp)
+    for h in hists:
+        J = [r["misfit"] for r in h]
+        _say("band misfits", J)
+        assert J[-1] < J[0]
+    _say("multiscale rms model error", fwi.rms_error(vp, truth), "->", fwi.rms_error(v, truth))
+    assert fwi.rms_error(v, truth) < fwi.rms_error(vp, truth)
