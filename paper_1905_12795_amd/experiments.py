@@ -115,8 +115,24 @@ def surrogate(workload, iters, seeds, K, log, members=1, kappa=0.0, misfit="l2")
     _emit(summ)
 
 
-def local_fwi(workload, search_iters, fwi_iters, seed, misfit="l2"):
-    """The paper's workflow: the EMPSO best model starts a local FWI of the same data."""
+def fwi_bands(g, prob, truth, bands):
+    """Stages of a multiscale FWI on data from the workload's observing source:
+    per band (f0, f_pass, f_stop, iterations), a problem with a Ricker source
+    of peak f0 and the observed data low-passed to the band."""
+    ob = g.get("observed")
+    if not ob:
+        raise ValueError("bands need a workload whose observed data come from another source")
+    stages = []
+    for f0, fp, fs, it in bands:
+        gb = dict(g, f0=f0)
+        pb = fd.Problem(gb, dt=prob.dt, nt=prob.nt)
+        stages.append((pb, search.observed_data_filtered(gb, pb, truth, ob["f0"], fp, fs), int(it)))
+    return stages
+
+
+def local_fwi(workload, search_iters, fwi_iters, seed, misfit="l2", bands=None):
+    """The paper's workflow: the EMPSO best model starts a local FWI of the same
+    data, in one band or, with `bands`, from low to high frequency."""
     from paper_1905_12795_amd import fwi
     g = dict(config(workload), misfit=misfit)
     prob = fd.Problem(g)
@@ -127,12 +143,23 @@ def local_fwi(workload, search_iters, fwi_iters, seed, misfit="l2"):
     best = np.asarray(h[-1]["best_position"], dtype=np.float32)
     v0 = fd.vp_from_nodes(prob, torch.tensor(best[None, :], device="cuda"))[0].contiguous()
     t0 = time.perf_counter()
-    v, hist = fwi.invert(prob, dobs, v0, fwi_iters, log=lambda r: _emit({"stage": "fwi", **r}))
+    if bands:
+        v = v0
+        for k, (pb, ob, it) in enumerate(fwi_bands(g, prob, truth, bands)):
+            v, hb = fwi.invert(pb, ob, v, it, log=lambda r, k=k: _emit({"stage": "fwi", "band": k, **r}))
+            _emit({"stage": "band", "band": k, "f0": bands[k][0], "misfit": hb[-1]["misfit"],
+                   "rms_error": fwi.rms_error(v, truth)})
+        v = torch.tensor(v, dtype=torch.float32, device="cuda")
+        hist = [{"misfit": fwi.model_misfit(prob, v, dobs)}]
+        v = v.cpu().numpy()
+    else:
+        v, hist = fwi.invert(prob, dobs, v0, fwi_iters, log=lambda r: _emit({"stage": "fwi", **r}))
     torch.cuda.synchronize()
     _emit({"workload": workload, "misfit": misfit, "seed": seed, "empso_misfit": h[-1]["best"],
            "true_model_misfit": fwi.model_misfit(prob, torch.tensor(truth, dtype=torch.float32, device="cuda"), dobs),
            "fwi_misfit": hist[-1]["misfit"],
-           "fwi_iterations": len(hist) - 1, "fwi_wall_s": time.perf_counter() - t0,
+           "fwi_iterations": int(sum(b[3] for b in bands)) if bands else len(hist) - 1,
+           "fwi_wall_s": time.perf_counter() - t0,
            "rms_error_empso": fwi.rms_error(v0.cpu().numpy(), truth), "rms_error_fwi": fwi.rms_error(v, truth)})
 
 
@@ -234,6 +261,8 @@ def main():
     f.add_argument("--fwi-iters", type=int, default=10)
     f.add_argument("--seed", type=int, default=1)
     f.add_argument("--misfit", default="l2", choices=["l2", "trace_normalised"])
+    f.add_argument("--bands", default=None,
+                   help="multiscale stages f0:f_pass:f_stop:iterations,... (Hz), low to high frequency")
     gr = sub.add_parser("gradient")
     gr.add_argument("--workload", default="realistic", choices=["tiny", "realistic", "irregular", "crime_free", "full"])
     gr.add_argument("--reps", type=int, default=2)
@@ -253,7 +282,8 @@ def main():
     elif a.cmd == "bandwidth":
         bandwidth(a.mib, a.reps)
     elif a.cmd == "fwi":
-        local_fwi(a.workload, a.search_iters, a.fwi_iters, a.seed, a.misfit)
+        bands = [tuple(float(x) for x in b.split(":")) for b in a.bands.split(",")] if a.bands else None
+        local_fwi(a.workload, a.search_iters, a.fwi_iters, a.seed, a.misfit, bands)
     else:
         surrogate(a.workload, a.iters, [int(x) for x in a.seeds.split(",")], a.K, a.log, a.members, a.kappa,
                   a.misfit)
