@@ -130,15 +130,17 @@ def fwi_bands(g, prob, truth, bands):
     return stages
 
 
-def local_fwi(workload, search_iters, fwi_iters, seed, misfit="l2", bands=None):
+def local_fwi(workload, search_iters, fwi_iters, seed, misfit="l2", bands=None, particles=0, log=None):
     """The paper's workflow: the EMPSO best model starts a local FWI of the same
     data, in one band or, with `bands`, from low to high frequency."""
     from paper_1905_12795_amd import fwi
     g = dict(config(workload), misfit=misfit)
+    if particles:
+        g["particles"] = int(particles)
     prob = fd.Problem(g)
     truth = true_model(g)
     dobs = search.observed_for(g, prob, truth)
-    h = search.run(g, dobs, prob, search_iters, "plain", seed=seed)
+    h = search.run(g, dobs, prob, search_iters, "plain", seed=seed, log_path=log)
     _emit({"stage": "empso", "iterations": search_iters, "best": h[-1]["best"], "wall_s": h[-1]["wall_s"]})
     best = np.asarray(h[-1]["best_position"], dtype=np.float32)
     v0 = fd.vp_from_nodes(prob, torch.tensor(best[None, :], device="cuda"))[0].contiguous()
@@ -155,7 +157,8 @@ def local_fwi(workload, search_iters, fwi_iters, seed, misfit="l2", bands=None):
     else:
         v, hist = fwi.invert(prob, dobs, v0, fwi_iters, log=lambda r: _emit({"stage": "fwi", **r}))
     torch.cuda.synchronize()
-    _emit({"workload": workload, "misfit": misfit, "seed": seed, "empso_misfit": h[-1]["best"],
+    _emit({"workload": workload, "misfit": misfit, "seed": seed, "particles": g["particles"],
+           "search_iterations": search_iters, "empso_misfit": h[-1]["best"],
            "true_model_misfit": fwi.model_misfit(prob, torch.tensor(truth, dtype=torch.float32, device="cuda"), dobs),
            "fwi_misfit": hist[-1]["misfit"],
            "fwi_iterations": int(sum(b[3] for b in bands)) if bands else len(hist) - 1,
@@ -261,6 +264,8 @@ def main():
     f.add_argument("--fwi-iters", type=int, default=10)
     f.add_argument("--seed", type=int, default=1)
     f.add_argument("--misfit", default="l2", choices=["l2", "trace_normalised"])
+    f.add_argument("--particles", type=int, default=0, help="swarm size (0: the workload's)")
+    f.add_argument("--log", default=None, help="per-iteration search log (JSON lines)")
     f.add_argument("--bands", default=None,
                    help="multiscale stages f0:f_pass:f_stop:iterations,... (Hz), low to high frequency")
     gr = sub.add_parser("gradient")
@@ -283,7 +288,7 @@ def main():
         bandwidth(a.mib, a.reps)
     elif a.cmd == "fwi":
         bands = [tuple(float(x) for x in b.split(":")) for b in a.bands.split(",")] if a.bands else None
-        local_fwi(a.workload, a.search_iters, a.fwi_iters, a.seed, a.misfit, bands)
+        local_fwi(a.workload, a.search_iters, a.fwi_iters, a.seed, a.misfit, bands, a.particles, a.log)
     else:
         surrogate(a.workload, a.iters, [int(x) for x in a.seeds.split(",")], a.K, a.log, a.members, a.kappa,
                   a.misfit)
