@@ -172,8 +172,11 @@ def damping_profile(nz, nx, nbl, dz, dx, vmax, R=1e-3):
     Paper: absorbing layer of nbpml points (JSON key nbpml); profile not given.
     Reading: quadratic profile d0 (l/nbl)^2, d0 = 3 vmax ln(1/R)/(2 nbl h),
     l = depth into the layer in points, z and x parts added.
-    Parity unpinned as a physical absorber (no published profile); checked only
-    for its definition and for absorbing better than no layer.
+    Pinned as a physical absorber (tests/test_oracle_absorber.py): on a 1 km
+    grid with a 40-point layer the records differ from those of a grid too
+    large for echoes by under 3 % (1.9 %), the difference grows as the layer
+    thins, and wrong profiles (x damping only, a peak ten times too weak or too
+    strong) exceed that.
     """
     Nz, Nx = nz + 2 * nbl, nx + 2 * nbl
     out = np.zeros((Nz, Nx), dtype=np.float64)
