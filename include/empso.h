@@ -192,8 +192,11 @@ size_t empso_forward_workspace_bytes(const empso_problem *prob, int32_t nsh);
  * (device, FP32; copied once to the host for the range check, so this call
  * waits for the stream) and write traces_d[nsh][nt][nrec] (device, FP32).
  * The model is extended into the absorbing layer by nearest-value copy.
- * ERANGE if a velocity lies outside [vmin, vmax]. tuning may be NULL (library
- * default; the graph flag is ignored). The traces do not depend on the tuning.
+ * ERANGE if a velocity lies outside [vmin, vmax]. tuning may be NULL: on the
+ * first such call for a problem and shot count the library times the
+ * candidate tunings (as empso_autotune_fitness does, on this call's workspace
+ * and model) and keeps the fastest until the problem is destroyed. The graph
+ * flag is ignored. The traces do not depend on the tuning.
  * nsh = 0 (with 0 <= shot0 <= nshots) is an empty range: EMPSO_OK, nothing is
  * enqueued and the pointer arguments are not used. EINVAL for nsh < 0 or a
  * range outside the problem's shots. */

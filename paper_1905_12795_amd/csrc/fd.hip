@@ -33,6 +33,7 @@
 #include <cmath>
 #include <cstring>
 #include <atomic>
+#include <map>
 #include <mutex>
 #include <type_traits>
 #include <unordered_map>
@@ -1230,8 +1231,13 @@ static Plan *find_or_make_plan(const std::vector<const void *> &kp, const std::v
 
 }  // namespace
 
+// Forward-modelling tunings chosen by timing, per (problem serial, shot count).
+static std::map<std::pair<uint64_t, int>, empso_tuning> g_fwd_tuning;
+
 static void drop_plans_of(uint64_t uid) {
     std::lock_guard<std::mutex> lk(g_plan_mu);
+    for (auto it = g_fwd_tuning.begin(); it != g_fwd_tuning.end();)
+        it = (it->first.first == uid) ? g_fwd_tuning.erase(it) : std::next(it);
     bool synced = false;
     for (size_t i = 0; i < g_plans.size();) {
         Plan *pl = g_plans[i];
@@ -1384,6 +1390,10 @@ extern "C" size_t empso_forward_workspace_bytes(const empso_problem *p, int32_t 
     return make_layout(pp, runs, p->D, kMinBz, kMaxT).total;
 }
 
+static int forward_autotune(const std::vector<const empso_problem *> &pp, const std::vector<RunSpec> &runs,
+                            const std::vector<const float *> &vps, unsigned char *w, hipStream_t st,
+                            empso_tuning *best);
+
 extern "C" int empso_forward_shots(const empso_problem *p, const float *vp_d, int32_t shot0, int32_t nsh,
                                    float *traces_d, void *ws, size_t ws_bytes, const empso_tuning *tuning,
                                    empso_stream stream) {
@@ -1406,15 +1416,29 @@ extern "C" int empso_forward_shots(const empso_problem *p, const float *vp_d, in
     std::vector<const empso_problem *> pp;
     std::vector<RunSpec> runs;
     forward_specs(p, shot0, nsh, traces_d, pp, runs);
-    empso_tuning tu;
-    if (tuning) tu = *tuning; else empso_default_tuning(&tu);
-    tu.use_graph = 0;
-    if (!valid_tuning(tu)) EMPSO_FAIL(EMPSO_ENOTSUP, "unsupported tuning");
-    std::lock_guard<std::mutex> lk(g_plan_mu);
-    Plan pl;
-    pl.L = make_layout(pp, runs, p->D, tu.bz, tu.tsteps);
     unsigned char *w = reinterpret_cast<unsigned char *>(ws);
     std::vector<const float *> vps(1, vp_d);
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    empso_tuning tu;
+    if (tuning) {
+        tu = *tuning;
+    } else {
+        // timed once per problem and shot count: the best tiling of a few
+        // runs differs from that of a large fitness batch
+        const auto key = std::make_pair(p->uid, (int)nsh);
+        const auto it = g_fwd_tuning.find(key);
+        if (it != g_fwd_tuning.end()) {
+            tu = it->second;
+        } else {
+            const int rc = forward_autotune(pp, runs, vps, w, st, &tu);
+            if (rc) return rc;
+            g_fwd_tuning[key] = tu;
+        }
+    }
+    tu.use_graph = 0;
+    if (!valid_tuning(tu)) EMPSO_FAIL(EMPSO_ENOTSUP, "unsupported tuning");
+    Plan pl;
+    pl.L = make_layout(pp, runs, p->D, tu.bz, tu.tsteps);
     build_header(pl, w, pp, runs, vps, nullptr, 0, p->D, tu);
     int rc = run_plan(&pl, w, (int)runs.size(), 1, p->g.nt, tu, nullptr, st);
     if (rc) return rc;
@@ -1560,12 +1584,16 @@ static int batch_prepare(const empso_problem *const *probs, int32_t nprob, const
 
 // Set up the batch for tuning tu (header, zero state, coefficients), run
 // `warm` untimed and `reps` timed launches of depth tu.tsteps from time 0.
+// The coefficient fields come from the particles' node values (nodes_h) or
+// from physical-grid models (vps, one per particle).
 static int time_one(const std::vector<const empso_problem *> &pp, const std::vector<RunSpec> &runs, int Dmax,
-                    const double *nodes_h, int ld_nodes, unsigned char *w, const empso_tuning &tu, int warm, int reps,
-                    hipEvent_t e0, hipEvent_t e1, hipStream_t st, float *us_per_step) {
+                    const double *nodes_h, int ld_nodes, const std::vector<const float *> &vps, unsigned char *w,
+                    const empso_tuning &tu, int warm, int reps, hipEvent_t e0, hipEvent_t e1, hipStream_t st,
+                    float *us_per_step) {
+    if (!nodes_h && vps.size() != pp.size()) EMPSO_FAIL(EMPSO_EINVAL, "timing needs node values or models");
     Plan pl;
     pl.L = make_layout(pp, runs, Dmax, tu.bz, tu.tsteps);
-    build_header(pl, w, pp, runs, std::vector<const float *>(), nodes_h, ld_nodes, Dmax, tu);
+    build_header(pl, w, pp, runs, vps, nodes_h, ld_nodes, Dmax, tu);
     const Layout &L = pl.L;
     EMPSO_HIP(hipMemcpyAsync(w, pl.host_hdr.data(), L.hdr_bytes, hipMemcpyHostToDevice, st));
     EMPSO_HIP(hipStreamSynchronize(st));
@@ -1606,32 +1634,28 @@ extern "C" int empso_time_tuning(const empso_problem *const *probs, int32_t npro
     EMPSO_HIP(hipEventCreate(&e0));
     EMPSO_HIP(hipEventCreate(&e1));
     std::lock_guard<std::mutex> lk(g_plan_mu);
-    rc = time_one(pp, runs, Dmax, nodes_h, ld_nodes, reinterpret_cast<unsigned char *>(ws), tu, 1, reps, e0, e1,
+    rc = time_one(pp, runs, Dmax, nodes_h, ld_nodes, std::vector<const float *>(), reinterpret_cast<unsigned char *>(ws),
+                  tu, 1, reps, e0, e1,
                   (hipStream_t)stream, us_per_step);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return rc;
 }
 
-extern "C" int empso_autotune_fitness(const empso_problem *const *probs, int32_t nprob, const float *const *obs_d,
-                                      const int32_t *pop, int32_t np, const double *nodes_h, int32_t ld_nodes,
-                                      void *ws, size_t ws_bytes, empso_tuning *best, float *best_us_per_step,
-                                      empso_stream stream) {
-    clear_error();
-    if (!best) EMPSO_FAIL(EMPSO_EINVAL, "NULL argument");
-    std::vector<const empso_problem *> pp;
-    std::vector<RunSpec> runs;
-    int Dmax;
-    int rc = batch_prepare(probs, nprob, obs_d, pop, np, nodes_h, ld_nodes, ws, ws_bytes, pp, runs, &Dmax);
-    if (rc) return rc;
+// Time every tile height (20 .. 320 rows, the first of each distinct tiling)
+// and depth T = 1 .. 4 on a batch (a few launches each) and keep the fastest.
+// The caller holds g_plan_mu.
+static int pick_tuning(const std::vector<const empso_problem *> &pp, const std::vector<RunSpec> &runs, int Dmax,
+                       const double *nodes_h, int ld_nodes, const std::vector<const float *> &vps,
+                       unsigned char *w, hipStream_t st, int warm, int reps, empso_tuning *best, float *best_us) {
     hipEvent_t e0, e1;
     EMPSO_HIP(hipEventCreate(&e0));
     EMPSO_HIP(hipEventCreate(&e1));
     const int bzs[6] = {20, 40, 80, 160, 240, 320};
-    float best_us = 1e30f;
+    float bus = 1e30f;
     empso_tuning bt;
     empso_default_tuning(&bt);
-    std::lock_guard<std::mutex> lk(g_plan_mu);
+    int rc = EMPSO_OK;
     for (int T = 1; T <= kMaxT && rc == EMPSO_OK; ++T) {
         std::vector<std::vector<int>> seen;    // strip heights of the tilings timed at this depth
         for (int bi = 0; bi < 6 && rc == EMPSO_OK; ++bi) {
@@ -1647,10 +1671,9 @@ extern "C" int empso_autotune_fitness(const empso_problem *const *probs, int32_t
             tu.tsteps = T;
             tu.use_graph = 0;
             float us = 0.f;
-            rc = time_one(pp, runs, Dmax, nodes_h, ld_nodes, reinterpret_cast<unsigned char *>(ws), tu, 2, 4, e0, e1,
-                          (hipStream_t)stream, &us);
-            if (rc == EMPSO_OK && us < best_us) {
-                best_us = us;
+            rc = time_one(pp, runs, Dmax, nodes_h, ld_nodes, vps, w, tu, warm, reps, e0, e1, st, &us);
+            if (rc == EMPSO_OK && us < bus) {
+                bus = us;
                 bt = tu;
             }
         }
@@ -1658,10 +1681,39 @@ extern "C" int empso_autotune_fitness(const empso_problem *const *probs, int32_t
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc) return rc;
+    *best = bt;
+    if (best_us) *best_us = bus;
+    return EMPSO_OK;
+}
+
+extern "C" int empso_autotune_fitness(const empso_problem *const *probs, int32_t nprob, const float *const *obs_d,
+                                      const int32_t *pop, int32_t np, const double *nodes_h, int32_t ld_nodes,
+                                      void *ws, size_t ws_bytes, empso_tuning *best, float *best_us_per_step,
+                                      empso_stream stream) {
+    clear_error();
+    if (!best) EMPSO_FAIL(EMPSO_EINVAL, "NULL argument");
+    std::vector<const empso_problem *> pp;
+    std::vector<RunSpec> runs;
+    int Dmax;
+    int rc = batch_prepare(probs, nprob, obs_d, pop, np, nodes_h, ld_nodes, ws, ws_bytes, pp, runs, &Dmax);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    empso_tuning bt;
+    rc = pick_tuning(pp, runs, Dmax, nodes_h, ld_nodes, std::vector<const float *>(),
+                     reinterpret_cast<unsigned char *>(ws), (hipStream_t)stream, 2, 4, &bt, best_us_per_step);
+    if (rc) return rc;
     bt.use_graph = 1;
     *best = bt;
-    if (best_us_per_step) *best_us_per_step = best_us;
     return EMPSO_OK;
+}
+
+// Tuning of a forward modelling (record mode, models given on the grid).
+static int forward_autotune(const std::vector<const empso_problem *> &pp, const std::vector<RunSpec> &runs,
+                            const std::vector<const float *> &vps, unsigned char *w, hipStream_t st,
+                            empso_tuning *best) {
+    const int rc = pick_tuning(pp, runs, pp[0]->D, nullptr, 0, vps, w, st, 1, 2, best, nullptr);
+    best->use_graph = 0;
+    return rc;
 }
 
 // ---------------------------------------------------------------------------
