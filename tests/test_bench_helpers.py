@@ -1,0 +1,54 @@
+"""Host logic of bench.py: the strip rule it mirrors and when committed
+counter summaries apply to a run."""
+import math
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+class _Tu:
+    def __init__(self, bz, tsteps):
+        self.bz, self.tsteps = bz, tsteps
+
+
+@pytest.mark.parametrize("Nz", [1, 7, 20, 33, 141, 381, 481, 681, 899])
+def test_strips_cover_the_grid_with_whole_march_blocks(Nz):
+    for bz in (20, 40, 80, 160, 240, 320):
+        for T in (1, 2, 3, 4):
+            h = bench.strip_rows(Nz, bz, T)
+            n = math.ceil(Nz / h)
+            # every strip holds rows, there are no more strips than ceil(Nz/bz),
+            # and a full strip's march (fill + rows) is whole 10-step blocks
+            assert h >= 1 and (n - 1) * h < Nz <= n * h
+            assert n <= math.ceil(Nz / bz)
+            assert (8 * (T - 1) + h) % 10 == 0
+
+
+def test_realistic_grid_heights():
+    # 381 padded rows: tile heights 240 and 320 give the same two strips
+    assert bench.strip_rows(381, 240, 4) == bench.strip_rows(381, 320, 4) == 196
+    assert bench.strip_rows(381, 160, 4) == 136
+
+
+def _summary(**kw):
+    d = {"kernel_source_sha256_16": bench.kernel_source_hash(), "updates_per_launch": 1000,
+         "tuning": {"bz": 320, "tsteps": 4}}
+    d.update(kw)
+    return d
+
+
+def test_counters_apply_only_to_the_same_kernel_and_tiles():
+    assert bench._counters_apply(_summary(), 1000, _Tu(320, 4), 381)
+    assert bench._counters_apply(_summary(), 1000, _Tu(240, 4), 381)          # same strips
+    assert not bench._counters_apply(_summary(), 1000, _Tu(160, 4), 381)      # other strips
+    assert not bench._counters_apply(_summary(), 1000, _Tu(320, 3), 381)      # other depth
+    assert not bench._counters_apply(_summary(), 999, _Tu(320, 4), 381)       # other batch
+    assert not bench._counters_apply(_summary(kernel_source_sha256_16="0" * 16), 1000, _Tu(320, 4), 381)
+
