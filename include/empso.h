@@ -238,7 +238,11 @@ size_t empso_fitness_workspace_bytes(const empso_problem *const *probs, int32_t 
  * over all shots of its problem of the l2 misfit, or of the trace-normalised
  * misfit when the problem selects it). All shots of all particles
  * advance together, one launch per time step or per block of time steps.
- *   probs[nprob]              problems (grids may differ; all must share nt)
+ *   probs[nprob]              problems (grids may differ; all must share nt; a batch
+ *                             whose grids all have dz = dx uses the isotropic grouping
+ *                             of the Laplacian, any other batch the general one, so
+ *                             a grid's fitness is bit-identical across batches of
+ *                             the same kind and equal to rounding otherwise)
  *   obs_d[nprob]              per problem, device FP32 [nshots][nt][nrec]
  *   prob_of_particle[np]      host, problem index of each particle
  *   nodes_h[np][ld_nodes]     host FP64 control-node velocities (ld_nodes >=

@@ -33,13 +33,15 @@ def gfd():
     return fd
 
 
-def _random_geom(seed):
+def _random_geom(seed, spacing=None):
     rng = np.random.default_rng(1000 + seed)
     g = copy.deepcopy(config("tiny"))
     nz, nx = int(rng.integers(8, 81)), int(rng.integers(8, 201))
     aniso = rng.random() < 0.4
     dz = float(rng.choice([6.0, 8.0, 12.0])) if aniso else 10.0
     dx = float(rng.choice([7.0, 10.0, 14.0])) if aniso else 10.0
+    if spacing is not None:
+        dz, dx = spacing
     cross = np.hypot((nz - 1) * dz, (nx - 1) * dx) / 1400.0          # slowest crossing time
     g.update(nz=nz, nx=nx, nbl=(0, 1, 3, 8, 20, 40)[seed % 6], dz=dz, dx=dx, f0=15.0,
              tmax=float(cross + 2.0 / 15.0))
@@ -124,3 +126,59 @@ def test_random_geometry_gradient_matches_oracle(gfd, seed):
     assert float(mis) == pytest.approx(Jo, rel=REL)
     m2, g2 = gfd.gradient(gp, vpt, obs, checkpoint_every=int(rng.integers(1, 40)))
     assert torch.equal(m2, mis) and torch.equal(g2, grad)
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_random_mixed_batch_equals_separate_batches(gfd, seed):
+    """Three random grids (shared dt and nt) in one batch, particles assigned
+    at random: the mixed batch equals the per-grid batches bit for bit at two
+    random tunings, and one particle per grid matches the oracle. The grids of
+    a batch share one spacing, equal (seeds 0, 2) or unequal (1, 3); seed 4
+    mixes equal- and unequal-spacing grids, which the batch runs with the
+    general Laplacian, so its equal-spacing runs match their own batch (the
+    isotropic grouping) to rounding instead of bit for bit."""
+    spacing = [(10.0, 10.0), (8.0, 12.0), (7.0, 7.0), (12.0, 6.0)]
+    if seed < 4:
+        geoms = [_random_geom(200 + 3 * seed + k, spacing[seed])[0] for k in range(3)]
+    else:
+        geoms = [_random_geom(200 + 3 * seed + k, s)[0] for k, s in enumerate([(10.0, 10.0), (8.0, 12.0), (10.0, 10.0)])]
+    rng = np.random.default_rng(300 + seed)
+    tmax = max(g["tmax"] for g in geoms)
+    for g in geoms:
+        g["tmax"] = tmax
+    ops = [ofd.Problem(g) for g in geoms]
+    dt = min(o.dt for o in ops)
+    nt = ofd.n_steps(tmax, dt)
+    ops = [ofd.Problem(g, dt=dt, nt=nt) for g in geoms]
+    gps = [gfd.Problem(g, dt=dt, nt=nt) for g in geoms]
+    Dmax = max(g["ncz"] * g["ncx"] for g in geoms)
+    npart = 7
+    pop = [int(q) for q in rng.integers(0, 3, npart)]
+    pop[:3] = [0, 1, 2]                                        # every grid has a particle
+    X = rng.uniform(1450, 2650, (npart, Dmax))
+    dobs = []
+    for o, g in zip(ops, geoms):
+        vp = ofd.vp_from_nodes(rng.uniform(1500, 2600, g["ncz"] * g["ncx"]), g["ncz"], g["ncx"], g["nz"], g["nx"])
+        dobs.append(ofd.forward_shots(o, vp).astype(np.float32))
+    obs = [torch.tensor(d, device="cuda") for d in dobs]
+    fb = gfd.FitnessBatch(gps, obs, pop)
+    outs = []
+    for _ in range(2):
+        tu = gfd.default_tuning()
+        tu.bz = int(rng.choice([20, 40, 80, 160, 240, 320]))
+        tu.tsteps = int(rng.integers(1, 5))
+        outs.append(fb(X, tuning=tu).cpu())
+        for q in range(3):
+            idx = [p for p in range(npart) if pop[p] == q]
+            sep = gfd.FitnessBatch([gps[q]], [obs[q]], [0] * len(idx))(X[idx][:, :geoms[q]["ncz"] * geoms[q]["ncx"]],
+                                                                      tuning=tu).cpu()
+            if seed < 4:
+                assert torch.equal(sep, outs[-1][idx]), (seed, q, tu.bz, tu.tsteps)
+            else:
+                assert torch.allclose(sep, outs[-1][idx], rtol=1e-5, atol=0), (seed, q, sep, outs[-1][idx])
+    assert torch.equal(outs[0], outs[1])
+    for q in range(3):
+        D = geoms[q]["ncz"] * geoms[q]["ncx"]
+        fo, _ = ofd.fitness_batch(ops[q], X[[q], :D].astype(np.float32).astype(np.float64), dobs[q])
+        n2 = float(np.sum(dobs[q].astype(np.float64) ** 2))
+        assert _fit_close(float(outs[0][q]), fo[0], n2), (seed, q, float(outs[0][q]), fo[0])
