@@ -6,7 +6,10 @@ finite-difference fitness. Network: x_hat = (x - lo)/(hi - lo), then hidden
 layers h = GELU(W h_prev + b) with the exact erf GELU, then a linear scalar
 output. Loss: mean squared error. Optimiser: Adam (Kingma and Ba, 2015).
 Pinned by: central finite differences of the loss (backward), GELU identities,
-and the closed form of Adam's first step (-lr * sign(g)).
+and closed forms of Adam: the first step (-lr * sign(g)), every step under a
+constant gradient (bias-corrected moments exactly g and g^2, so each step is
+-lr g / (|g| + eps)) and under a gradient of alternating sign (the first
+moment a geometric sum).
 """
 import math
 

@@ -134,3 +134,73 @@ def test_adam_first_step_is_signed_lr():
     p2, _, _ = mlp.adam_step(params, grads, m, v, 1, 1e-2)
     assert np.allclose(p2[0][0], [[1.0 - 1e-2, -2.0 + 1e-2]], atol=1e-9)
     assert np.allclose(p2[0][1], [0.5 + 1e-2], atol=1e-9)
+
+
+def _adam_run(adam, grads_of_step, p0, steps, lr, eps=1e-8):
+    """Parameters after `steps` Adam updates of a single-tensor model whose
+    gradient at step t (from 1) is grads_of_step(t)."""
+    params = [(np.array(p0, dtype=np.float64), np.zeros(1))]
+    m, v = mlp.zeros_like(params), mlp.zeros_like(params)
+    out = []
+    for t in range(1, steps + 1):
+        grads = [(grads_of_step(t), np.zeros(1))]
+        params, m, v = adam(params, grads, m, v, t, lr, eps=eps)
+        out.append(params[0][0].copy())
+    return out
+
+
+def test_adam_constant_gradient_closed_form():
+    # With g fixed, m_t = (1 - b1^t) g and v_t = (1 - b2^t) g^2, so the
+    # bias-corrected moments are exactly g and g^2 at every step and each
+    # step moves by -lr g / (|g| + eps): after t steps p0 - t lr g / (|g| + eps).
+    g = np.array([[3.0, -0.02, 1e-8, -4e-9, 250.0]])
+    p0 = np.array([[0.5, -1.0, 2.0, 0.0, 7.0]])
+    lr, eps = 1e-2, 1e-8
+    traj = _adam_run(mlp.adam_step, lambda t: g, p0, 8, lr, eps)
+    for t, p in enumerate(traj, start=1):
+        want = p0 - t * lr * g / (np.abs(g) + eps)
+        assert np.allclose(p, want, rtol=1e-12, atol=1e-14), (t, p, want)
+
+
+def test_adam_alternating_gradient_closed_form():
+    # g_t = (-1)^(t+1) g: m_t = (1 - b1) g (-1)^(t+1) (1 - (-b1)^t) / (1 + b1)
+    # (a geometric sum), v_t = (1 - b2^t) g^2, step -lr m_hat / (sqrt(v_hat) + eps).
+    b1, b2, lr, eps = 0.9, 0.999, 1e-3, 1e-8
+    g = np.array([[2.0, -0.5, 1e-3]])
+    p0 = np.zeros((1, 3))
+    traj = _adam_run(mlp.adam_step, lambda t: g * (-1.0) ** (t + 1), p0, 7, lr, eps)
+    p = p0.copy()
+    for t in range(1, 8):
+        m = (1 - b1) * g * (-1.0) ** (t + 1) * (1 - (-b1) ** t) / (1 + b1)
+        v = (1 - b2 ** t) * g * g
+        p = p - lr * (m / (1 - b1 ** t)) / (np.sqrt(v / (1 - b2 ** t)) + eps)
+        assert np.allclose(traj[t - 1], p, rtol=1e-12, atol=1e-15), t
+
+
+ADAM_MUTATIONS = {
+    "bias correction frozen at step 1": ("mh = M2 / (1 - b1 ** step)", "mh = M2 / (1 - b1)"),
+    "second-moment correction frozen at step 1": ("vh = V2 / (1 - b2 ** step)", "vh = V2 / (1 - b2)"),
+    "first moment without (1 - b1)": ("M2 = b1 * M_ + (1 - b1) * G_", "M2 = b1 * M_ + G_"),
+    "eps inside the square root": ("np.sqrt(vh) + eps", "np.sqrt(vh + eps)"),
+    "moment decays swapped": ("M2 = b1 * M_ + (1 - b1) * G_", "M2 = b2 * M_ + (1 - b2) * G_"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(ADAM_MUTATIONS))
+def test_planted_adam_mistake_is_caught(monkeypatch, name):
+    import inspect
+    import textwrap
+    old, new = ADAM_MUTATIONS[name]
+    src = textwrap.dedent(inspect.getsource(mlp.adam_step))
+    assert old in src, name
+    ns = dict(mlp.__dict__)
+    exec(compile(src.replace(old, new, 1), "<mutant>", "exec"), ns)
+    monkeypatch.setattr(mlp, "adam_step", ns["adam_step"])
+    caught = 0
+    for pin in (test_adam_first_step_is_signed_lr, test_adam_constant_gradient_closed_form,
+                test_adam_alternating_gradient_closed_form):
+        try:
+            pin()
+        except AssertionError:
+            caught += 1
+    assert caught > 0, name
