@@ -116,3 +116,86 @@ def test_training_reduces_loss_on_smooth_target(sur):
     rho = np.corrcoef(np.argsort(np.argsort(pred)), np.argsort(np.argsort(ft)))[0, 1]
     print("spearman", rho, flush=True)
     assert rho > 0.7, rho
+
+
+def _flat(t):
+    """A flat device vector as the oracle's one-tensor parameter list (FP64)."""
+    return [(t.detach().cpu().numpy().astype(np.float64), np.zeros(0))]
+
+
+def test_adam_steps_match_the_oracle_update(sur):
+    """Six training steps: each step's parameters, first and second moments
+    equal the oracle's Adam update (bias correction at that step) applied to
+    the GPU's own gradient and the GPU's previous state, to FP32 rounding.
+    Bars from the FP32 arithmetic, relative to the size of the terms (the
+    first moment b1 m + (1 - b1) g cancels when g changes sign): first moment
+    within 1e-6 of b1 |m| + (1 - b1) |g|; second moment within 5e-5 of
+    b2 v + (1 - b2) g^2 (the kernel's FP32 beta2 makes 1 - beta2 differ from
+    0.001 by 1.3e-5 relative); the parameter change within twice the
+    propagation of both through the update plus the rounding of the stored
+    parameter. (An FP32 emulation of the update stays below half of each.)"""
+    lo, hi, X, fit = _case(24, 64, 200, 12)
+    net = sur.MLP(lo, hi, H=64, seed=13)
+    Xd = torch.tensor(X, dtype=torch.float32, device="cuda")
+    fd_ = torch.tensor(fit, device="cuda")
+    lr, mu, sigma = 2e-3, 3.0, 1.0
+    for step in range(1, 7):
+        _, g = net.grad(Xd, fd_, None, mu, sigma)
+        p0, m0, v0 = _flat(net.params), _flat(net.m), _flat(net.v)
+        net.train_step(Xd, fd_, None, mu, sigma, lr)
+        gh = _flat(g)
+        pw, mw, vw = omlp.adam_step(p0, gh, m0, v0, step, lr)
+        gg, mp, vp, pp = gh[0][0], m0[0][0], v0[0][0], p0[0][0]
+        m_gpu = net.m.cpu().numpy().astype(np.float64)
+        v_gpu = net.v.cpu().numpy().astype(np.float64)
+        p_gpu = net.params.detach().cpu().numpy().astype(np.float64)
+        scale_m = 0.9 * np.abs(mp) + 0.1 * np.abs(gg)
+        scale_v = 0.999 * vp + 0.001 * gg * gg
+        assert np.all(np.abs(m_gpu - mw[0][0]) <= 1e-6 * scale_m + 1e-30), step
+        assert np.all(np.abs(v_gpu - vw[0][0]) <= 5e-5 * scale_v + 1e-38), step
+        denom = np.sqrt(vw[0][0] / (1 - 0.999 ** step)) + 1e-8
+        bound = lr * (1e-6 * scale_m + 5e-5 * np.abs(mw[0][0])) / (1 - 0.9 ** step) / denom \
+            + 2.0 ** -24 * (np.abs(pp) + np.abs(p_gpu))
+        err = np.abs((p_gpu - pp) - (pw[0][0] - pp))
+        print("step", step, "largest update error / bound", float(np.max(err / bound)), flush=True)
+        assert np.all(err <= 2 * bound), step
+
+
+def test_five_training_steps_follow_the_oracle(sur):
+    """Five Adam steps from the same FP32 parameters: GPU (BF16 MFMA
+    gradients) against the FP64 oracle's own gradients and Adam updates.
+    Bar: cosine >= 0.99 between the two parameter changes of every tensor,
+    over the parameters whose first oracle gradient exceeds 1e-4 (Adam moves
+    every parameter by about lr whatever its gradient's size, so the sign of
+    a gradient below BF16's resolution is noise on either side); the cosine
+    over all parameters is printed."""
+    D, H, n = 60, 256, 512
+    lo, hi, X, fit = _case(D, H, n, 14)
+    net = sur.MLP(lo, hi, H=H, seed=15)
+    lf = np.log(fit.astype(np.float64))
+    mu, sigma = float(lf.mean()), float(lf.std())
+    Xd = torch.tensor(X, dtype=torch.float32, device="cuda")
+    fd_ = torch.tensor(fit, device="cuda")
+    lr = 1e-3
+    layers = _oracle_layers(net, sur)
+    start = [(W.copy(), b.copy()) for W, b in layers]
+    t = (lf - np.float32(mu)) / np.float32(sigma)
+    lo_, hi_ = lo.astype(np.float32).astype(np.float64), hi.astype(np.float32).astype(np.float64)
+    m, v = omlp.zeros_like(layers), omlp.zeros_like(layers)
+    g_first = None
+    for step in range(1, 6):
+        _, gr = omlp.loss_and_grads(layers, X, t, lo_, hi_)
+        g_first = g_first or gr
+        layers, m, v = omlp.adam_step(layers, gr, m, v, step, lr)
+        net.train_step(Xd, fd_, None, mu, sigma, lr)
+    got = sur.unflatten_params(net.params.cpu().numpy(), D, H)
+    for k, ((gW, gb), (oW, ob), (sW, sb), (fW, fb_)) in enumerate(zip(got, layers, start, g_first)):
+        for which, (a, b, s, g0) in enumerate(((gW, oW, sW, fW), (gb, ob, sb, fb_))):
+            da, db = np.ravel(a - s), np.ravel(b - s)
+            big = np.abs(np.ravel(g0)) > 1e-4
+            cos_all = float(da @ db / (np.linalg.norm(da) * np.linalg.norm(db)))
+            cos = float(da[big] @ db[big] / (np.linalg.norm(da[big]) * np.linalg.norm(db[big])))
+            print("layer", k, "W" if which == 0 else "b", "cosine", cos, "(all %.5f, %d of %d large)"
+                  % (cos_all, int(big.sum()), big.size), flush=True)
+            assert big.sum() > 0
+            assert cos >= 0.99, (k, which, cos)
