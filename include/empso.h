@@ -142,7 +142,7 @@ typedef struct {
  * bit-identical results; only the speed changes. */
 typedef struct {
     int32_t variant;         /* reserved, 0                                             */
-    int32_t bz;              /* target output rows per tile, a multiple of 20 in 20..320;
+    int32_t bz;              /* target output rows per tile, a multiple of 20 in 20..1280;
                               * each grid's rows are split into equal strips of about
                               * this height, rounded up so that a strip's march (its
                               * 8 (tsteps - 1) queue-fill steps plus its rows) is a
@@ -165,9 +165,14 @@ const char *empso_last_error(void);
  * Testing approach section: second order in time, eighth order in space. */
 int empso_stable_dt(double vmax, double dz, double dx, double *dt_out);
 
-/* Create a problem. Validates the geometry (EINVAL, ECFL, ENOTSUP), builds the
- * wavelet, damping and receiver tables and uploads them to the current
- * device. *out receives the handle (NULL on error). */
+/* Create a problem (Testing approach section: the grid, time axis, source,
+ * receivers and control-node layout of the paper's modelling setup).
+ * Validates the geometry (EINVAL, ECFL, ENOTSUP), builds the wavelet, damping
+ * and receiver tables and uploads them to the current device. *out receives
+ * the handle (NULL on error). ENOTSUP for a grid whose stored field (padded
+ * grid plus a 16-point zero ring, rows rounded up to 64 floats) exceeds 2^27
+ * floats (512 MiB): the kernels address a run's four fields with 32-bit
+ * byte offsets. */
 int empso_problem_create(const empso_geometry *geom, empso_problem **out);
 
 /* Destroy a problem created by empso_problem_create (NULL is ignored). The
@@ -188,7 +193,10 @@ int empso_vp_from_nodes(const empso_problem *prob, int32_t nmodels, const float 
  * on invalid arguments). */
 size_t empso_forward_workspace_bytes(const empso_problem *prob, int32_t nsh);
 
-/* Model shots shot0 .. shot0+nsh-1 in the physical-grid model vp_d[nz][nx]
+/* Forward modelling of shots (Testing approach section: each shot is
+ * modelled with the finite-difference scheme above and recorded at every
+ * receiver at every time step; these are the traces the misfit compares).
+ * Model shots shot0 .. shot0+nsh-1 in the physical-grid model vp_d[nz][nx]
  * (device, FP32; copied once to the host for the range check, so this call
  * waits for the stream) and write traces_d[nsh][nt][nrec] (device, FP32).
  * The model is extended into the absorbing layer by nearest-value copy.
@@ -207,8 +215,13 @@ int empso_forward_shots(const empso_problem *prob, const float *vp_d, int32_t sh
 /* Workspace bytes for empso_misfit over n elements. */
 size_t empso_misfit_workspace_bytes(int64_t n);
 
-/* out_d[0] = 1/2 sum_k (a_d[k] - b_d[k])^2 over n elements (device, FP32
- * inputs, FP64 accumulation in a fixed order, FP32 result). Deterministic. */
+/* The paper's l2 misfit between two trace arrays (Testing approach section:
+ * a model is scored by the l2 norm of its traces' difference from the
+ * observed ones; here squared and halved):
+ * out_d[0] = 1/2 sum_k (a_d[k] - b_d[k])^2 over n elements (device, FP32
+ * inputs, FP64 accumulation in a fixed order, FP32 result). Deterministic.
+ * n = 0 gives 0. EINVAL for NULL pointers or n < 0; EWORKSPACE if ws_bytes
+ * is below empso_misfit_workspace_bytes(n). */
 int empso_misfit(const float *a_d, const float *b_d, int64_t n, float *out_d,
                  void *ws, size_t ws_bytes, empso_stream stream);
 
@@ -259,12 +272,41 @@ int empso_fitness_batch(const empso_problem *const *probs, int32_t nprob,
                         void *ws, size_t ws_bytes, const empso_tuning *tuning,
                         empso_stream stream);
 
+/* The same evaluation as empso_fitness_batch, run in blocks of time steps:
+ * one call performs the transitions n -> n+1 for n_begin <= n < n_end of
+ * every run of the batch, so that a caller can bound the duration of a call
+ * or interleave other work with a long evaluation. The state between calls
+ * lives in the workspace.
+ *   n_begin = 0       starts an evaluation: the particles' nodes_h (host
+ *                     FP64, range-checked as in empso_fitness_batch) are
+ *                     uploaded, the wavefields cleared and the coefficient
+ *                     fields built;
+ *   n_begin > 0       continues the evaluation that the previous call on this
+ *                     batch, workspace and tuning left at step n_begin
+ *                     (EINVAL otherwise); nodes_h is not read and may be NULL;
+ *   n_end = nt - 1    finishes it: the last time sample is taken and
+ *                     fitness_d[np] written. Before that call fitness_d is
+ *                     not touched.
+ * 0 <= n_begin <= n_end <= nt - 1; n_begin must be 0 or a multiple of
+ * tuning->tsteps and n_end nt - 1 or a multiple of tuning->tsteps (EINVAL).
+ * The launch sequence is the one empso_fitness_batch replays, so the fitness
+ * values are bit-identical to it for the same tuning. Calls run without
+ * graph replay (use_graph is ignored). np = 0 is an empty batch (EMPSO_OK,
+ * nothing enqueued). */
+int empso_fitness_batch_steps(const empso_problem *const *probs, int32_t nprob,
+                              const float *const *obs_d, const int32_t *prob_of_particle, int32_t np,
+                              const double *nodes_h, int32_t ld_nodes, float *fitness_d,
+                              int32_t n_begin, int32_t n_end,
+                              void *ws, size_t ws_bytes, const empso_tuning *tuning,
+                              empso_stream stream);
+
 /* Default tuning used when NULL is passed. */
 int empso_default_tuning(empso_tuning *out);
 
 /* Autotuner: with the same arguments as empso_fitness_batch, time a few
  * launches of the finite-difference kernel for every tile height of 20, 40,
- * 80, 160, 240 and 320 rows and temporal-blocking depth on this batch (a
+ * 80, 160, 240, 320, 480, 720 and 1040 rows and temporal-blocking depth on
+ * this batch (a
  * height that gives every grid the same strips as a lower one launches the
  * same tiles and is skipped) and write the fastest tuning to
  * *best (graph replay on) and its time per time step in microseconds to

@@ -78,6 +78,10 @@ SIGNATURES = {
     "empso_fitness_batch": (ctypes.c_int, [_P(_vp), ctypes.c_int32, _P(_vp), _P(ctypes.c_int32),
                                            ctypes.c_int32, _P(ctypes.c_double), ctypes.c_int32, _vp,
                                            _vp, ctypes.c_size_t, _P(Tuning), _vp]),
+    "empso_fitness_batch_steps": (ctypes.c_int, [_P(_vp), ctypes.c_int32, _P(_vp), _P(ctypes.c_int32),
+                                                 ctypes.c_int32, _P(ctypes.c_double), ctypes.c_int32, _vp,
+                                                 ctypes.c_int32, ctypes.c_int32, _vp, ctypes.c_size_t, _P(Tuning),
+                                                 _vp]),
     "empso_default_tuning": (ctypes.c_int, [_P(Tuning)]),
     "empso_mlp_param_count": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32]),
     "empso_mlp_bf16_count": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32]),

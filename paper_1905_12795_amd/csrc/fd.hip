@@ -200,6 +200,15 @@ extern "C" int empso_problem_create(const empso_geometry *gp, empso_problem **ou
     const int64_t Nz64 = (int64_t)g.nz + 2 * (int64_t)g.nbl, Nx64 = (int64_t)g.nx + 2 * (int64_t)g.nbl;
     if (Nz64 > (1 << 20) || Nx64 > (1 << 20) || (Nz64 + 8) * (Nx64 + 72) > (int64_t)1 << 31)
         EMPSO_FAIL(EMPSO_ENOTSUP, "grid too large");
+    {
+        // the stencil kernel addresses a run's four fields through one buffer
+        // resource with 32-bit byte offsets: 4 field bytes must stay below 2^31
+        const int64_t S64 = (Nx64 + 2 * kRing + 63) / 64 * 64;
+        const int64_t fb64 = ((Nz64 + 2 * kRing) * S64 * (int64_t)sizeof(float) + 255) / 256 * 256;
+        if (fb64 >= ((int64_t)1 << 29))
+            EMPSO_FAIL(EMPSO_ENOTSUP, "grid too large: a stored field takes %lld bytes (limit 512 MiB)",
+                       (long long)fb64);
+    }
     if (g.dt > stable_dt_raw(g.vmax, g.dz, g.dx) * (1.0 + 1e-12))
         EMPSO_FAIL(EMPSO_ECFL, "dt = %g exceeds the stability limit %g at vmax = %g", g.dt,
                    stable_dt_raw(g.vmax, g.dz, g.dx), g.vmax);
@@ -913,6 +922,11 @@ struct RunSpec {
 };
 
 static const int kMinBz = 20;      // smallest tile height (sizes the tile tables)
+static const int kMaxBz = 1280;    // largest tile height
+// tile heights the autotuner tries (each grid is split into balanced strips
+// of about that height; tall grids of many runs march best in one or two)
+static const int kTuneBz[] = {20, 40, 80, 160, 240, 320, 480, 720, 1040};
+static const int kNumTuneBz = (int)(sizeof(kTuneBz) / sizeof(kTuneBz[0]));
 static const int kTailBz = 40;     // tile height of the single-step launches that finish the record
 
 static int out_cols(int T) { return kTileX - 8 * T; }
@@ -1010,6 +1024,7 @@ struct Plan {
     bool upload_pending = false;
     hipGraphExec_t exec = nullptr;
     hipStream_t cap_stream = nullptr;
+    int progress = -1;                     // time step an evaluation run in blocks has reached (-1: none)
     // release the graph and staging (callers make sure nothing is queued)
     void release() {
         if (exec) (void)hipGraphExecDestroy(exec);
@@ -1021,6 +1036,7 @@ struct Plan {
         upload_done = nullptr;
         pinned = nullptr;
         upload_pending = false;
+        progress = -1;
     }
     ~Plan() { release(); }
 };
@@ -1054,22 +1070,27 @@ static int launch_tb(int T, bool iso, const RunDesc *runs, const int4 *tiles, in
     return EMPSO_ENOTSUP;
 }
 
-// Enqueue the whole evaluation (zero state, coefficients, time loop in blocks
-// of T steps and single steps for the remainder, final sample, optional
-// reduction) on stream st.
-static int enqueue_all(const Plan &pl, unsigned char *ws, int nruns, int np, int nt, const empso_tuning &tu,
-                       float *fitness, hipStream_t st) {
+// Enqueue the time steps n -> n+1, n0 <= n < n1, of the evaluation on stream
+// st: from n0 = 0 first the state is cleared and the coefficients built; the
+// time loop runs launches of T steps and single steps for a remainder; at
+// n1 = nt - 1 the last sample is taken and (if fitness) the reduction runs.
+// n0 is 0 or a multiple of T, so the pair holding the state at n0 is the
+// parity of the n0 / T launches before it.
+static int enqueue_range(const Plan &pl, unsigned char *ws, int nruns, int np, int nt, const empso_tuning &tu,
+                         float *fitness, int n0, int n1, hipStream_t st) {
     const Layout &L = pl.L;
     const RunDesc *runs = reinterpret_cast<const RunDesc *>(ws + L.runs_off);
     const int4 *tiles = reinterpret_cast<const int4 *>(ws + L.tiles_off);
     const int4 *tiles1 = reinterpret_cast<const int4 *>(ws + L.tiles1_off);
-    const int64_t n4 = (int64_t)(L.total - L.state_off) / 16;
-    k_zero<<<2048, 256, 0, st>>>(reinterpret_cast<float4 *>(ws + L.state_off), n4);
-    k_coef<<<dim3(512, np), 256, 0, st>>>(reinterpret_cast<const CoefDesc *>(ws + L.coef_off));
-    int n = 0, par = 0;
-    while (n < nt - 1) {
+    if (n0 == 0) {
+        const int64_t n4 = (int64_t)(L.total - L.state_off) / 16;
+        k_zero<<<2048, 256, 0, st>>>(reinterpret_cast<float4 *>(ws + L.state_off), n4);
+        k_coef<<<dim3(512, np), 256, 0, st>>>(reinterpret_cast<const CoefDesc *>(ws + L.coef_off));
+    }
+    int n = n0, par = (n0 / tu.tsteps) & 1;
+    while (n < n1) {
         int rc;
-        if (n + tu.tsteps <= nt - 1) {
+        if (n + tu.tsteps <= n1) {
             rc = launch_tb(tu.tsteps, L.iso, runs, tiles, L.ntiles, n, par, st);
             n += tu.tsteps;
         } else {
@@ -1079,9 +1100,17 @@ static int enqueue_all(const Plan &pl, unsigned char *ws, int nruns, int np, int
         if (rc) return rc;
         par ^= 1;
     }
-    k_sample<<<dim3(8, nruns), 256, 0, st>>>(runs, nruns, nt - 1, par);
-    if (fitness) k_fitness<<<np, 256, 0, st>>>(runs, reinterpret_cast<const int *>(ws + L.prun_off), fitness);
+    if (n1 == nt - 1) {
+        k_sample<<<dim3(8, nruns), 256, 0, st>>>(runs, nruns, nt - 1, par);
+        if (fitness) k_fitness<<<np, 256, 0, st>>>(runs, reinterpret_cast<const int *>(ws + L.prun_off), fitness);
+    }
     return EMPSO_OK;
+}
+
+// The whole evaluation on stream st.
+static int enqueue_all(const Plan &pl, unsigned char *ws, int nruns, int np, int nt, const empso_tuning &tu,
+                       float *fitness, hipStream_t st) {
+    return enqueue_range(pl, ws, nruns, np, nt, tu, fitness, 0, nt - 1, st);
 }
 
 static void fill_tiles(int4 *td, const std::vector<const empso_problem *> &pp, const std::vector<RunSpec> &runs,
@@ -1163,9 +1192,8 @@ static void build_header(Plan &pl, unsigned char *ws, const std::vector<const em
     fill_tiles(reinterpret_cast<int4 *>(h.data() + L.tiles1_off), pp, runs, kTailBz, 1);
 }
 
-static int run_plan(Plan *pl, unsigned char *ws, int nruns, int np, int nt, const empso_tuning &tu, float *fitness,
-                    hipStream_t st) {
-    // upload the header through the pinned staging buffer
+// Upload the plan's descriptor header through its pinned staging buffer.
+static int upload_header(Plan *pl, unsigned char *ws, hipStream_t st) {
     if (!pl->pinned) {
         EMPSO_HIP(hipHostMalloc(reinterpret_cast<void **>(&pl->pinned), pl->L.hdr_bytes, hipHostMallocDefault));
         EMPSO_HIP(hipEventCreateWithFlags(&pl->upload_done, hipEventDisableTiming));
@@ -1175,6 +1203,14 @@ static int run_plan(Plan *pl, unsigned char *ws, int nruns, int np, int nt, cons
     EMPSO_HIP(hipMemcpyAsync(ws, pl->pinned, pl->L.hdr_bytes, hipMemcpyHostToDevice, st));
     EMPSO_HIP(hipEventRecord(pl->upload_done, st));
     pl->upload_pending = true;
+    return EMPSO_OK;
+}
+
+static int run_plan(Plan *pl, unsigned char *ws, int nruns, int np, int nt, const empso_tuning &tu, float *fitness,
+                    hipStream_t st) {
+    const int urc = upload_header(pl, ws, st);
+    if (urc) return urc;
+    pl->progress = -1;
 
     if (!tu.use_graph) {
         int rc = enqueue_all(*pl, ws, nruns, np, nt, tu, fitness, st);
@@ -1202,6 +1238,13 @@ static int run_plan(Plan *pl, unsigned char *ws, int nruns, int np, int nt, cons
     }
     EMPSO_HIP(hipGraphLaunch(pl->exec, st));
     return EMPSO_OK;
+}
+
+// Any call that writes a workspace ends every evaluation in blocks on it.
+// The caller holds g_plan_mu.
+static void forget_progress(const void *ws) {
+    for (Plan *p : g_plans)
+        if (!p->key_ptrs.empty() && p->key_ptrs[0] == ws) p->progress = -1;
 }
 
 static Plan *find_or_make_plan(const std::vector<const void *> &kp, const std::vector<int> &ki, bool *fresh) {
@@ -1257,7 +1300,7 @@ static void drop_plans_of(uint64_t uid) {
 namespace {
 
 static bool valid_tuning(const empso_tuning &t) {
-    return t.bz >= 20 && t.bz <= 320 && t.bz % 20 == 0 && t.tsteps >= 1 && t.tsteps <= kMaxT && t.prefetch == 1 &&
+    return t.bz >= 20 && t.bz <= kMaxBz && t.bz % 20 == 0 && t.tsteps >= 1 && t.tsteps <= kMaxT && t.prefetch == 1 &&
            (t.use_graph == 0 || t.use_graph == 1);
 }
 
@@ -1354,15 +1397,11 @@ extern "C" size_t empso_traces_misfit_workspace_bytes(const empso_problem *p, in
     return align_up(sizeof(double) * 4 * (size_t)std::max(nsh, 1) * p->g.nrec, 256);
 }
 
-extern "C" int empso_traces_misfit(const empso_problem *p, const float *traces_d, const float *obs_d, int32_t nsh,
-                                   float *out_d, void *ws, size_t ws_bytes, empso_stream stream) {
-    clear_error();
-    if (!p || !out_d || !ws || (nsh > 0 && (!traces_d || !obs_d))) EMPSO_FAIL(EMPSO_EINVAL, "NULL argument");
-    if (nsh < 0) EMPSO_FAIL(EMPSO_EINVAL, "nsh must be >= 0");
-    if (ws_bytes < empso_traces_misfit_workspace_bytes(p, nsh)) EMPSO_FAIL(EMPSO_EWORKSPACE, "workspace too small");
-    hipStream_t st = (hipStream_t)stream;
+// Enqueue the traces misfit with its scratch (4 nsh nrec doubles) at ws.
+static int enqueue_traces_misfit(const empso_problem *p, const float *traces_d, const float *obs_d, int32_t nsh,
+                                 float *out_d, double *ws, hipStream_t st) {
     const int nrec = p->g.nrec;
-    double *sums = reinterpret_cast<double *>(ws);                 // [nsh][3][nrec]
+    double *sums = ws;                                             // [nsh][3][nrec]
     double *per = sums + (size_t)3 * nsh * nrec;                   // [nsh][nrec]
     const int norm = p->g.misfit == EMPSO_MISFIT_TRACE_NORMALISED ? 1 : 0;
     if (nsh > 0) {
@@ -1373,6 +1412,17 @@ extern "C" int empso_traces_misfit(const empso_problem *p, const float *traces_d
     EMPSO_HIP(hipGetLastError());
     return EMPSO_OK;
 }
+
+extern "C" int empso_traces_misfit(const empso_problem *p, const float *traces_d, const float *obs_d, int32_t nsh,
+                                   float *out_d, void *ws, size_t ws_bytes, empso_stream stream) {
+    clear_error();
+    if (!p || !out_d || !ws || (nsh > 0 && (!traces_d || !obs_d))) EMPSO_FAIL(EMPSO_EINVAL, "NULL argument");
+    if (nsh < 0) EMPSO_FAIL(EMPSO_EINVAL, "nsh must be >= 0");
+    if (ws_bytes < empso_traces_misfit_workspace_bytes(p, nsh)) EMPSO_FAIL(EMPSO_EWORKSPACE, "workspace too small");
+    return enqueue_traces_misfit(p, traces_d, obs_d, nsh, out_d, reinterpret_cast<double *>(ws),
+                                 (hipStream_t)stream);
+}
+
 
 static void forward_specs(const empso_problem *p, int32_t shot0, int32_t nsh, float *traces_d,
                           std::vector<const empso_problem *> &pp, std::vector<RunSpec> &runs) {
@@ -1437,6 +1487,7 @@ extern "C" int empso_forward_shots(const empso_problem *p, const float *vp_d, in
     }
     tu.use_graph = 0;
     if (!valid_tuning(tu)) EMPSO_FAIL(EMPSO_ENOTSUP, "unsupported tuning");
+    forget_progress(w);
     Plan pl;
     pl.L = make_layout(pp, runs, p->D, tu.bz, tu.tsteps);
     build_header(pl, w, pp, runs, vps, nullptr, 0, p->D, tu);
@@ -1476,13 +1527,23 @@ extern "C" size_t empso_fitness_workspace_bytes(const empso_problem *const *prob
     return make_layout(pp, runs, Dmax, kMinBz, kMaxT).total;
 }
 
-extern "C" int empso_fitness_batch(const empso_problem *const *probs, int32_t nprob, const float *const *obs_d,
-                                   const int32_t *pop, int32_t np, const double *nodes_h, int32_t ld_nodes,
-                                   float *fitness_d, void *ws, size_t ws_bytes, const empso_tuning *tuning,
-                                   empso_stream stream) {
-    clear_error();
-    if (np == 0) return EMPSO_OK;               // empty batch: nothing to evaluate or enqueue
-    if (!probs || !obs_d || !pop || !nodes_h || !fitness_d || !ws) EMPSO_FAIL(EMPSO_EINVAL, "NULL argument");
+// Validation and plan lookup shared by empso_fitness_batch and
+// empso_fitness_batch_steps. check_nodes: range-check nodes_h on the host.
+// On success *plp is the batch's plan (the caller holds g_plan_mu) and
+// *fresh tells whether it was built anew.
+struct BatchCall {
+    std::vector<const empso_problem *> pp;
+    std::vector<RunSpec> runs;
+    int Dmax = 0;
+    empso_tuning tu;
+};
+
+static int batch_call(const empso_problem *const *probs, int32_t nprob, const float *const *obs_d, const int32_t *pop,
+                      int32_t np, const double *nodes_h, int32_t ld_nodes, const float *fitness_d, void *ws,
+                      size_t ws_bytes, const empso_tuning *tuning, bool check_nodes, BatchCall &bc,
+                      std::vector<const void *> &kp, std::vector<int> &ki, std::vector<uint64_t> &uids) {
+    if (!probs || !obs_d || !pop || (check_nodes && !nodes_h) || !fitness_d || !ws)
+        EMPSO_FAIL(EMPSO_EINVAL, "NULL argument");
     if (nprob < 1 || np < 1) EMPSO_FAIL(EMPSO_EINVAL, "nprob >= 1 and np >= 0 required");
     if (reinterpret_cast<uintptr_t>(ws) % 256) EMPSO_FAIL(EMPSO_EINVAL, "workspace must be 256-byte aligned");
     for (int q = 0; q < nprob; ++q) {
@@ -1490,35 +1551,30 @@ extern "C" int empso_fitness_batch(const empso_problem *const *probs, int32_t np
         if (!obs_d[q]) EMPSO_FAIL(EMPSO_EINVAL, "obs_d[%d] is NULL", q);
         if (probs[q]->g.nt != probs[0]->g.nt) EMPSO_FAIL(EMPSO_ENOTSUP, "all problems of a batch must share nt");
     }
-    empso_tuning tu;
-    if (tuning) tu = *tuning; else empso_default_tuning(&tu);
-    if (!valid_tuning(tu)) EMPSO_FAIL(EMPSO_ENOTSUP, "unsupported tuning");
-    std::vector<const empso_problem *> pp;
-    std::vector<RunSpec> runs;
-    int Dmax;
-    int rc = batch_specs(probs, nprob, obs_d, pop, np, pp, runs, &Dmax);
+    if (tuning) bc.tu = *tuning; else empso_default_tuning(&bc.tu);
+    if (!valid_tuning(bc.tu)) EMPSO_FAIL(EMPSO_ENOTSUP, "unsupported tuning");
+    int rc = batch_specs(probs, nprob, obs_d, pop, np, bc.pp, bc.runs, &bc.Dmax);
     if (rc) return rc;
-    if (ld_nodes < Dmax) EMPSO_FAIL(EMPSO_EINVAL, "ld_nodes = %d < %d", ld_nodes, Dmax);
-    // range check on the host in FP64: bilinear interpolation is a convex
-    // combination, so every grid velocity then lies in [vmin, vmax] and the
-    // stability condition checked at problem creation holds everywhere.
-    for (int k = 0; k < np; ++k) {
-        const empso_problem *p = pp[k];
-        for (int d = 0; d < p->D; ++d) {
-            const double v = nodes_h[(size_t)k * ld_nodes + d];
-            if (!(v >= p->g.vmin && v <= p->g.vmax))
-                EMPSO_FAIL(EMPSO_ERANGE, "node %d of particle %d = %g outside [%g, %g]", d, k, v, p->g.vmin,
-                           p->g.vmax);
+    if (check_nodes) {
+        if (ld_nodes < bc.Dmax) EMPSO_FAIL(EMPSO_EINVAL, "ld_nodes = %d < %d", ld_nodes, bc.Dmax);
+        // range check on the host in FP64: bilinear interpolation is a convex
+        // combination, so every grid velocity then lies in [vmin, vmax] and the
+        // stability condition checked at problem creation holds everywhere.
+        for (int k = 0; k < np; ++k) {
+            const empso_problem *p = bc.pp[k];
+            for (int d = 0; d < p->D; ++d) {
+                const double v = nodes_h[(size_t)k * ld_nodes + d];
+                if (!(v >= p->g.vmin && v <= p->g.vmax))
+                    EMPSO_FAIL(EMPSO_ERANGE, "node %d of particle %d = %g outside [%g, %g]", d, k, v, p->g.vmin,
+                               p->g.vmax);
+            }
         }
     }
-    const size_t need = make_layout(pp, runs, Dmax, kMinBz, kMaxT).total;
+    const size_t need = make_layout(bc.pp, bc.runs, bc.Dmax, kMinBz, kMaxT).total;
     if (ws_bytes < need) EMPSO_FAIL(EMPSO_EWORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
 
     // plan key: buffers, problems by serial number (a destroyed problem's
     // address can come back for a new one), batch composition and tuning
-    std::vector<const void *> kp;
-    std::vector<int> ki;
-    std::vector<uint64_t> uids;
     kp.push_back(ws);
     kp.push_back(fitness_d);
     for (int q = 0; q < nprob; ++q) {
@@ -1527,29 +1583,94 @@ extern "C" int empso_fitness_batch(const empso_problem *const *probs, int32_t np
         ki.push_back((int)(probs[q]->uid >> 31));
     }
     ki.push_back(np);
-    ki.push_back(tu.bz);
-    ki.push_back(tu.tsteps);
-    ki.push_back(tu.prefetch);
-    ki.push_back(tu.use_graph);
+    ki.push_back(bc.tu.bz);
+    ki.push_back(bc.tu.tsteps);
+    ki.push_back(bc.tu.prefetch);
     for (int k = 0; k < np; ++k) ki.push_back(pop[k]);
+    return EMPSO_OK;
+}
 
-    std::lock_guard<std::mutex> lk(g_plan_mu);
-    bool fresh;
-    Plan *pl = find_or_make_plan(kp, ki, &fresh);
-    Layout Lnow = make_layout(pp, runs, Dmax, tu.bz, tu.tsteps);
-    if (!fresh && !same_layout(pl->L, Lnow)) {
+// The batch's plan, rebuilt if its layout changed. The caller holds g_plan_mu.
+static Plan *batch_plan(BatchCall &bc, const std::vector<const void *> &kp, const std::vector<int> &ki,
+                        const std::vector<uint64_t> &uids, bool *fresh) {
+    Plan *pl = find_or_make_plan(kp, ki, fresh);
+    Layout Lnow = make_layout(bc.pp, bc.runs, bc.Dmax, bc.tu.bz, bc.tu.tsteps);
+    if (!*fresh && !same_layout(pl->L, Lnow)) {
         // never replay a plan built for another layout: rebuild it
         (void)hipDeviceSynchronize();
         pl->release();
-        fresh = true;
+        *fresh = true;
     }
-    if (fresh) {
+    if (*fresh) {
         pl->L = std::move(Lnow);
         pl->uids = uids;
     }
+    return pl;
+}
+
+extern "C" int empso_fitness_batch(const empso_problem *const *probs, int32_t nprob, const float *const *obs_d,
+                                   const int32_t *pop, int32_t np, const double *nodes_h, int32_t ld_nodes,
+                                   float *fitness_d, void *ws, size_t ws_bytes, const empso_tuning *tuning,
+                                   empso_stream stream) {
+    clear_error();
+    if (np == 0) return EMPSO_OK;               // empty batch: nothing to evaluate or enqueue
+    BatchCall bc;
+    std::vector<const void *> kp;
+    std::vector<int> ki;
+    std::vector<uint64_t> uids;
+    int rc = batch_call(probs, nprob, obs_d, pop, np, nodes_h, ld_nodes, fitness_d, ws, ws_bytes, tuning, true, bc,
+                        kp, ki, uids);
+    if (rc) return rc;
+    ki.push_back(bc.tu.use_graph);
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    bool fresh;
+    Plan *pl = batch_plan(bc, kp, ki, uids, &fresh);
+    forget_progress(ws);
     unsigned char *w = reinterpret_cast<unsigned char *>(ws);
-    build_header(*pl, w, pp, runs, std::vector<const float *>(), nodes_h, ld_nodes, Dmax, tu);
-    return run_plan(pl, w, (int)runs.size(), np, pp[0]->g.nt, tu, fitness_d, (hipStream_t)stream);
+    build_header(*pl, w, bc.pp, bc.runs, std::vector<const float *>(), nodes_h, ld_nodes, bc.Dmax, bc.tu);
+    return run_plan(pl, w, (int)bc.runs.size(), np, bc.pp[0]->g.nt, bc.tu, fitness_d, (hipStream_t)stream);
+}
+
+extern "C" int empso_fitness_batch_steps(const empso_problem *const *probs, int32_t nprob, const float *const *obs_d,
+                                         const int32_t *pop, int32_t np, const double *nodes_h, int32_t ld_nodes,
+                                         float *fitness_d, int32_t n_begin, int32_t n_end, void *ws, size_t ws_bytes,
+                                         const empso_tuning *tuning, empso_stream stream) {
+    clear_error();
+    if (np == 0) return EMPSO_OK;               // empty batch: nothing to evaluate or enqueue
+    BatchCall bc;
+    std::vector<const void *> kp;
+    std::vector<int> ki;
+    std::vector<uint64_t> uids;
+    int rc = batch_call(probs, nprob, obs_d, pop, np, nodes_h, ld_nodes, fitness_d, ws, ws_bytes, tuning,
+                        n_begin == 0, bc, kp, ki, uids);
+    if (rc) return rc;
+    const int nt = bc.pp[0]->g.nt, T = bc.tu.tsteps;
+    if (n_begin < 0 || n_end < n_begin || n_end > nt - 1)
+        EMPSO_FAIL(EMPSO_EINVAL, "need 0 <= n_begin <= n_end <= nt - 1 = %d (got %d, %d)", nt - 1, n_begin, n_end);
+    if (n_begin % T != 0 || (n_end != nt - 1 && n_end % T != 0))
+        EMPSO_FAIL(EMPSO_EINVAL, "n_begin must be a multiple of tsteps = %d, n_end one too or nt - 1", T);
+    ki.push_back(2);                            // block calls never share a plan with graph replay
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    bool fresh;
+    Plan *pl = batch_plan(bc, kp, ki, uids, &fresh);
+    if (n_begin > 0 && (fresh || pl->progress != n_begin))
+        EMPSO_FAIL(EMPSO_EINVAL, "no evaluation of this batch on this workspace stands at step %d", n_begin);
+    const int at = pl->progress;
+    forget_progress(ws);
+    pl->progress = at;
+    unsigned char *w = reinterpret_cast<unsigned char *>(ws);
+    hipStream_t st = (hipStream_t)stream;
+    if (n_begin == 0) {
+        build_header(*pl, w, bc.pp, bc.runs, std::vector<const float *>(), nodes_h, ld_nodes, bc.Dmax, bc.tu);
+        rc = upload_header(pl, w, st);
+        if (rc) return rc;
+    }
+    pl->progress = -1;
+    rc = enqueue_range(*pl, w, (int)bc.runs.size(), np, nt, bc.tu, fitness_d, n_begin, n_end, st);
+    if (rc) EMPSO_FAIL(rc, "launch failed");
+    EMPSO_HIP(hipGetLastError());
+    pl->progress = n_end < nt - 1 ? n_end : -1;
+    return EMPSO_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -1591,6 +1712,7 @@ static int time_one(const std::vector<const empso_problem *> &pp, const std::vec
                     const empso_tuning &tu, int warm, int reps, hipEvent_t e0, hipEvent_t e1, hipStream_t st,
                     float *us_per_step) {
     if (!nodes_h && vps.size() != pp.size()) EMPSO_FAIL(EMPSO_EINVAL, "timing needs node values or models");
+    forget_progress(w);
     Plan pl;
     pl.L = make_layout(pp, runs, Dmax, tu.bz, tu.tsteps);
     build_header(pl, w, pp, runs, vps, nodes_h, ld_nodes, Dmax, tu);
@@ -1642,7 +1764,7 @@ extern "C" int empso_time_tuning(const empso_problem *const *probs, int32_t npro
     return rc;
 }
 
-// Time every tile height (20 .. 320 rows, the first of each distinct tiling)
+// Time every tile height of kTuneBz (the first of each distinct tiling)
 // and depth T = 1 .. 4 on a batch (a few launches each) and keep the fastest.
 // The caller holds g_plan_mu.
 static int pick_tuning(const std::vector<const empso_problem *> &pp, const std::vector<RunSpec> &runs, int Dmax,
@@ -1651,23 +1773,23 @@ static int pick_tuning(const std::vector<const empso_problem *> &pp, const std::
     hipEvent_t e0, e1;
     EMPSO_HIP(hipEventCreate(&e0));
     EMPSO_HIP(hipEventCreate(&e1));
-    const int bzs[6] = {20, 40, 80, 160, 240, 320};
+
     float bus = 1e30f;
     empso_tuning bt;
     empso_default_tuning(&bt);
     int rc = EMPSO_OK;
     for (int T = 1; T <= kMaxT && rc == EMPSO_OK; ++T) {
         std::vector<std::vector<int>> seen;    // strip heights of the tilings timed at this depth
-        for (int bi = 0; bi < 6 && rc == EMPSO_OK; ++bi) {
+        for (int bi = 0; bi < kNumTuneBz && rc == EMPSO_OK; ++bi) {
             // tile heights that give every grid of the batch the same strips
             // launch the same tiles: time the first of them only
             std::vector<int> sig;
-            for (const empso_problem *p : pp) sig.push_back(strip_height(p, bzs[bi], T));
+            for (const empso_problem *p : pp) sig.push_back(strip_height(p, kTuneBz[bi], T));
             if (std::find(seen.begin(), seen.end(), sig) != seen.end()) continue;
             seen.push_back(sig);
             empso_tuning tu;
             empso_default_tuning(&tu);
-            tu.bz = bzs[bi];
+            tu.bz = kTuneBz[bi];
             tu.tsteps = T;
             tu.use_graph = 0;
             float us = 0.f;

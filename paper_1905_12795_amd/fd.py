@@ -270,6 +270,25 @@ class FitnessBatch:
                                     ctypes.byref(us), _stream()))
         return float(us.value)
 
+    def steps(self, nodes, n_begin, n_end, tuning=None):
+        """Time steps n_begin .. n_end - 1 of an evaluation of the batch
+        (library: empso_fitness_batch_steps). n_begin = 0 starts one from
+        `nodes` (host float64 [np][D]); later blocks continue it (nodes may be
+        None); the block that ends at nt - 1 writes the fitness values, which
+        the returned device tensor then holds."""
+        t = tuning if tuning is not None else self.tuning
+        xp = None
+        if nodes is not None:
+            x = np.ascontiguousarray(np.asarray(nodes, dtype=np.float64))
+            if x.shape != (self.np, self.Dmax):
+                raise ValueError("nodes must be [%d][%d]" % (self.np, self.Dmax))
+            self._steps_nodes = x                     # kept alive for the call
+            xp = x.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        check(lib.empso_fitness_batch_steps(self._ph, len(self.probs), self._oh, self._pop_ptr(), self.np, xp,
+                                            self.Dmax, _ptr(self.out), int(n_begin), int(n_end), _ptr(self.ws),
+                                            self.ws.numel(), ctypes.byref(t), _stream()))
+        return self.out
+
     def __call__(self, nodes, tuning=None):
         """nodes: host float64 [np][D] (row stride Dmax). Returns the device fitness tensor."""
         x = np.ascontiguousarray(np.asarray(nodes, dtype=np.float64))

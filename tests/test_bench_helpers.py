@@ -20,7 +20,7 @@ class _Tu:
 
 @pytest.mark.parametrize("Nz", [1, 7, 20, 33, 141, 381, 481, 681, 899])
 def test_strips_cover_the_grid_with_whole_march_blocks(Nz):
-    for bz in (20, 40, 80, 160, 240, 320):
+    for bz in (20, 40, 80, 160, 240, 320, 480, 720, 1040, 1280):
         for T in (1, 2, 3, 4):
             h = bench.strip_rows(Nz, bz, T)
             n = math.ceil(Nz / h)

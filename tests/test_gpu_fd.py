@@ -154,6 +154,46 @@ def test_tiling_graph_and_repeat_are_bitwise_invariant(gfd):
         assert torch.equal(o, outs[0][1]), key
 
 
+def test_fitness_in_time_blocks_equals_one_call(gfd):
+    """An evaluation run in blocks of time steps (empso_fitness_batch_steps)
+    gives the one-call fitness bit for bit, for several depths and block
+    lengths; continuing a block that does not stand where the last one ended,
+    or after another call overwrote the workspace, is refused."""
+    from paper_1905_12795_amd._lib import EmpsoError
+    g = _small_geom()
+    op, gp = _pair(gfd, g)
+    rng = np.random.default_rng(16)
+    dobs = torch.tensor(rng.standard_normal((3, gp.nt, gp.nrec)).astype(np.float32) * 1e-3, device="cuda")
+    X = rng.uniform(1400, 2700, (6, 12))
+    fb = gfd.FitnessBatch([gp], [dobs], [0] * 6)
+    last = gp.nt - 1
+    for T, block in ((1, 7), (2, 40), (3, 99), (4, 4), (4, 200)):
+        tu = gfd.default_tuning()
+        tu.bz, tu.tsteps = 80, T
+        ref = fb(X, tuning=tu).clone()
+        fb.out.fill_(-1.0)
+        n = 0
+        while n < last:
+            n1 = min(n + block, last)
+            got = fb.steps(X if n == 0 else None, n, n1, tuning=tu)
+            if n1 < last:
+                assert float(got.min()) == -1.0            # untouched before the last block
+            n = n1
+        assert torch.equal(got, ref), (T, block)
+    tu = gfd.default_tuning()
+    tu.bz, tu.tsteps = 80, 4
+    fb.steps(X, 0, 40, tuning=tu)
+    with pytest.raises(EmpsoError) as ei:
+        fb.steps(None, 80, 120, tuning=tu)                 # the evaluation stands at 40
+    assert ei.value.status == -1
+    with pytest.raises(EmpsoError):
+        fb.steps(None, 42, 80, tuning=tu)                  # not a multiple of the depth
+    fb.steps(None, 40, 80, tuning=tu)
+    fb(X, tuning=tu)                                       # overwrites the workspace
+    with pytest.raises(EmpsoError):
+        fb.steps(None, 80, 120, tuning=tu)
+
+
 def test_wide_grid_interior_tiles_bitwise_invariant(gfd):
     """A grid wide enough for tiles with no damping column: all tunings agree bit for bit."""
     g = _small_geom()
@@ -249,7 +289,7 @@ def test_autotuner_picks_a_valid_tuning_with_identical_results(gfd):
     fb = gfd.FitnessBatch([gp], [dobs], [0] * 4)
     ref = fb(X).clone()
     best, us = fb.autotune(X)
-    assert best["bz"] in (20, 40, 80, 160, 240, 320) and 1 <= best["tsteps"] <= 4 and best["use_graph"] == 1
+    assert best["bz"] in (20, 40, 80, 160, 240, 320, 480, 720, 1040) and 1 <= best["tsteps"] <= 4 and best["use_graph"] == 1
     assert us > 0
     assert fb.time_tuning(X, fb.tuning, reps=2) > 0
     assert torch.equal(fb(X), ref)

@@ -117,6 +117,28 @@ def test_null_arguments(L):
     assert t.tsteps >= 1 and t.bz > 0
 
 
+def test_grid_above_the_32_bit_field_limit_is_rejected(L):
+    # 16352 stored rows (ring included) of 8192 floats fill 2^29 bytes: four
+    # such fields no longer fit 32-bit byte offsets below 2^31
+    g = _geom(L, nz=16352, nx=8160, nbl=0)
+    h = ctypes.c_void_p(123)
+    assert L.lib.empso_problem_create(ctypes.byref(g), ctypes.byref(h)) == -6
+    assert h.value is None
+    assert b"512 MiB" in L.lib.empso_last_error()
+    # one row less passes the size check (it then needs a device for its tables)
+    g = _geom(L, nz=16351, nx=8160, nbl=0)
+    rc = L.lib.empso_problem_create(ctypes.byref(g), ctypes.byref(h))
+    assert rc != -6, L.lib.empso_last_error()
+    if rc == 0:
+        L.lib.empso_problem_destroy(h)
+
+
+def test_fitness_steps_null_and_empty(L):
+    args = (None, 1, None, None, 1, None, 1, None, 0, 10, None, 0, None, None)
+    assert L.lib.empso_fitness_batch_steps(*args) == -1
+    assert L.lib.empso_fitness_batch_steps(None, 0, None, None, 0, None, 0, None, 0, 0, None, 0, None, None) == 0
+
+
 def test_empty_batch_is_a_no_op(L):
     # np = 0: nothing to evaluate, nothing enqueued and no device call made
     assert L.lib.empso_fitness_batch(None, 0, None, None, 0, None, 0, None, None, 0, None, None) == 0
