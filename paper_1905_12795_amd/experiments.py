@@ -6,6 +6,10 @@
   python -m paper_1905_12795_amd.experiments throughput --workload full --particles 8
       fitness of `particles` particles x 32 shots on the 601 x 1841 grid at
       5 m (a slice of the full workload's 128-particle iteration).
+  python -m paper_1905_12795_amd.experiments surrogate-paired --workload realistic --pretrain pairs.npz
+      plain EMPSO (128 particles) against the surrogate screen (1024
+      candidates, the best-ranked 64 evaluated, a network pretrained on 20k
+      FD pairs) and a random screen, on 12 paired seeds, with 95 % intervals.
   python -m paper_1905_12795_amd.experiments surrogate --workload realistic --iters 15 --seeds 1
       plain vs surrogate-screened vs randomly screened EMPSO on the same
       seeds; FD evaluations and wall time until each reaches 1.01 x the plain
@@ -112,6 +116,75 @@ def surrogate(workload, iters, seeds, K, log, members=1, kappa=0.0, misfit="l2")
         summ.update({mode + "_final": mean[mode][-1]["best"], mode + "_evals_to_plain": e,
                      mode + "_wall_to_plain": t})
     summ["curves"] = {m: [round(r["best"], 4) for r in mean[m]] for m in mean}
+    _emit(summ)
+
+
+def paired_ci(d, level=0.95):
+    """Mean of paired differences d and its two-sided t confidence interval."""
+    from scipy import stats
+    d = np.asarray(d, dtype=np.float64)
+    m = float(d.mean())
+    if d.size < 2:
+        return m, float("nan"), float("nan")
+    h = float(stats.t.ppf(0.5 + level / 2, d.size - 1) * d.std(ddof=1) / np.sqrt(d.size))
+    return m, m - h, m + h
+
+
+def surrogate_paired(workload, iters, seeds, N, K, M, pretrain_path, pretrain_n, pretrain_steps, log):
+    """Plain EMPSO (N particles, all evaluated) against the surrogate screen
+    (N particles x K candidate moves screened, the best-ranked M particles
+    evaluated, a network pretrained on pretrain_n (particle, fitness) pairs of
+    earlier FD runs) and against the same screen with a random ranking, on
+    paired seeds. Per seed: FD evaluations and wall time until the best misfit
+    reaches 1.01 x the plain run's final value (the screened runs stop there,
+    or at the plain run's evaluation budget: censored). Summary: the mean
+    paired differences with 95 % t intervals."""
+    g = dict(config(workload))
+    g["particles"] = N
+    prob = fd.Problem(g)
+    dobs = search.observed_for(g, prob, true_model(g))
+    if pretrain_path and os.path.exists(pretrain_path):
+        d = np.load(pretrain_path, allow_pickle=False)
+        X0, f0 = d["X"], d["f"]
+        _emit({"stage": "pretraining pairs loaded", "path": pretrain_path, "n": int(len(f0))})
+    else:
+        t0 = time.perf_counter()
+        X0, f0 = search.pretrain_pairs(prob, dobs, g["node_lo"], g["node_hi"], pretrain_n, seed=1000)
+        _emit({"stage": "pretraining pairs evaluated", "n": int(len(f0)), "seconds": time.perf_counter() - t0})
+        if pretrain_path:
+            np.savez(pretrain_path, X=X0, f=f0)
+    rows = []
+    for seed in seeds:
+        hp = search.run(g, dobs, prob, iters, "plain", seed=seed, log_path=log)
+        target = 1.01 * hp[-1]["best"]
+        budget = hp[-1]["evaluations"]
+        ep, tp = search.evals_to_reach(hp, target)
+        row = {"seed": seed, "plain_final": hp[-1]["best"], "target": target, "budget": budget,
+               "plain_evals": ep, "plain_wall": tp, "plain_wall_all": hp[-1]["wall_s"]}
+        for mode in ("screened", "random"):
+            h = search.run(g, dobs, prob, 10 * iters, mode, seed=seed, K=K, evaluate=M, log_path=log,
+                           pretrain=(X0, f0), pretrain_steps=pretrain_steps, target=target, max_evals=budget,
+                           gen=iters)
+            e, t = search.evals_to_reach(h, target)
+            row[mode + "_reached"] = bool(np.isfinite(e))
+            row[mode + "_evals"] = e if np.isfinite(e) else h[-1]["evaluations"]
+            row[mode + "_wall"] = t if np.isfinite(t) else h[-1]["wall_s"]
+            row[mode + "_final"] = h[-1]["best"]
+            if mode == "screened":
+                rh = [r["surrogate_rho"] for r in h if "surrogate_rho" in r]
+                row["screened_mean_rho"] = float(np.mean(rh)) if rh else None
+        rows.append(row)
+        _emit(dict(row, workload=workload))
+    summ = {"workload": workload, "seeds": list(seeds), "particles": N, "K": K, "evaluated": M,
+            "plain_iterations": iters, "pretrain_pairs": int(len(f0)), "pretrain_steps": pretrain_steps,
+            "censored_at_budget": {m: int(sum(not r[m + "_reached"] for r in rows)) for m in ("screened", "random")}}
+    for a, b in (("plain", "screened"), ("plain", "random"), ("random", "screened")):
+        for q in ("evals", "wall"):
+            m, lo, hi = paired_ci([r[a + "_" + q] - r[b + "_" + q] for r in rows])
+            summ["%s_minus_%s_%s" % (a, b, q)] = {"mean": m, "ci95": [lo, hi]}
+    for m in ("plain", "screened", "random"):
+        summ[m + "_mean_evals"] = float(np.mean([r[m + "_evals"] for r in rows]))
+        summ[m + "_mean_wall"] = float(np.mean([r[m + "_wall"] for r in rows]))
     _emit(summ)
 
 
@@ -258,6 +331,17 @@ def main():
     s.add_argument("--members", type=int, default=1, help="networks in the surrogate ensemble")
     s.add_argument("--kappa", type=float, default=0.0, help="score = members' mean + kappa * spread")
     s.add_argument("--misfit", default="l2", choices=["l2", "trace_normalised"])
+    sp = sub.add_parser("surrogate-paired")
+    sp.add_argument("--workload", default="realistic", choices=["mini", "realistic"])
+    sp.add_argument("--iters", type=int, default=12, help="iterations of the plain search")
+    sp.add_argument("--seeds", default="1,2,3,4,5,6,7,8,9,10,11,12")
+    sp.add_argument("--particles", type=int, default=128)
+    sp.add_argument("--K", type=int, default=8)
+    sp.add_argument("--evaluate", type=int, default=64)
+    sp.add_argument("--pretrain", default=None, help=".npz of (X, f) pairs: loaded if present, else written")
+    sp.add_argument("--pretrain-n", type=int, default=20000)
+    sp.add_argument("--pretrain-steps", type=int, default=3000)
+    sp.add_argument("--log", default=None)
     f = sub.add_parser("fwi")
     f.add_argument("--workload", default="realistic", choices=["realistic", "irregular", "crime_free"])
     f.add_argument("--search-iters", type=int, default=15)
@@ -286,6 +370,9 @@ def main():
         mlp_timing(a.reps)
     elif a.cmd == "bandwidth":
         bandwidth(a.mib, a.reps)
+    elif a.cmd == "surrogate-paired":
+        surrogate_paired(a.workload, a.iters, [int(x) for x in a.seeds.split(",")], a.particles, a.K, a.evaluate,
+                         a.pretrain, a.pretrain_n, a.pretrain_steps, a.log)
     elif a.cmd == "fwi":
         bands = [tuple(float(x) for x in b.split(":")) for b in a.bands.split(",")] if a.bands else None
         local_fwi(a.workload, a.search_iters, a.fwi_iters, a.seed, a.misfit, bands, a.particles, a.log)

@@ -86,7 +86,8 @@ def spearman(a, b):
 
 
 def run(geom, dobs, prob, iterations, mode="plain", seed=0, K=16, warmup=2, sur_kw=None, log_path=None,
-        autotune=True, elitist=True, target=None):
+        autotune=True, elitist=True, target=None, evaluate=None, pretrain=None, pretrain_steps=0, max_evals=None,
+        gen=None):
     """Run the search; returns the list of per-iteration records.
 
     Record fields: iteration, best, mean, median, evaluations (FD, cumulative),
@@ -95,21 +96,36 @@ def run(geom, dobs, prob, iterations, mode="plain", seed=0, K=16, warmup=2, sur_
     surrogate_rho (Spearman correlation between the surrogate's prediction and
     the FD misfit of the evaluated particles, measured before it trains on
     them) and surrogate_mae (mean absolute error of the standardised
-    log-misfit). If `target` is given the run stops once best <= target.
+    log-misfit). If `target` is given the run stops once best <= target, and
+    with `max_evals` once the FD evaluations reach it. `gen` (default
+    `iterations`) is the swarm's nominal iteration count, which sets when the
+    elitist mutation starts.
+
+    Screened and random modes: `evaluate` = M < N sends only M of the N
+    particles to the FD fitness each iteration (ScreenedEMPSO); `pretrain` =
+    (X, f) are (particle, fitness) pairs from earlier FD runs that the
+    surrogate holds and trains on (`pretrain_steps` Adam steps) before the
+    search starts (untimed; the swarm then uses it from the first iteration).
     """
     N = geom["particles"]
+    M = N if (mode == "plain" or evaluate is None) else int(evaluate)
     lo, hi = geom["node_lo"], geom["node_hi"]
-    fb = fd.FitnessBatch([prob], [dobs], [0] * N)
-    kw = dict(gen=iterations, seed=seed, elitist=elitist)
+    fb = fd.FitnessBatch([prob], [dobs], [0] * M)
+    kw = dict(gen=gen or iterations, seed=seed, elitist=elitist)
     if mode == "plain":
         swarm = EMPSO(lo, hi, N, **kw)
         sur = None
     elif mode == "screened":
         sur = Surrogate(lo, hi, seed=seed, **(sur_kw or {}))
-        swarm = ScreenedEMPSO(lo, hi, N, sur, K=K, warmup=warmup, **kw)
+        if pretrain is not None:
+            sur.add(pretrain[0], pretrain[1])
+            sur.train(steps=pretrain_steps)
+            warmup = 0
+        swarm = ScreenedEMPSO(lo, hi, N, sur, K=K, warmup=warmup, evaluate=M, **kw)
     elif mode == "random":
         sur = None
-        swarm = ScreenedEMPSO(lo, hi, N, RandomRanker(seed), K=K, warmup=warmup, **kw)
+        swarm = ScreenedEMPSO(lo, hi, N, RandomRanker(seed), K=K, warmup=0 if pretrain is not None else warmup,
+                              evaluate=M, **kw)
     else:
         raise ValueError(mode)
     if autotune:
@@ -122,7 +138,7 @@ def run(geom, dobs, prob, iterations, mode="plain", seed=0, K=16, warmup=2, sur_
         x = swarm.ask()
         f = fb(x).cpu().numpy().astype(np.float64)
         rec_extra = {}
-        if isinstance(sur, Surrogate) and sur.count >= N * warmup:
+        if isinstance(sur, Surrogate) and swarm.k >= swarm.warmup:
             pred = sur.predict(x)
             ok = np.isfinite(f)
             lf = (np.log(np.maximum(f[ok], 1e-30)) - sur.mu) / sur.sigma
@@ -138,11 +154,30 @@ def run(geom, dobs, prob, iterations, mode="plain", seed=0, K=16, warmup=2, sur_
             logf.flush()
         if target is not None and rec["best"] <= target:
             break
+        if max_evals is not None and rec["evaluations"] >= max_evals:
+            break
     if logf:
         logf.close()
     if out:
         out[-1]["best_position"] = [float(x) for x in swarm.g]     # gbest nodes (FP64), not logged
     return out
+
+
+def pretrain_pairs(prob, dobs, lo, hi, n, seed, batch=128):
+    """(X [n][D], fitness [n]) of n particles drawn uniformly in the search box
+    (seeded), evaluated by the FD fitness in batches: the data a surrogate
+    can be trained on before a search."""
+    from workloads.models import uniform_particles
+    X = uniform_particles(n, lo, hi, seed)
+    fb = fd.FitnessBatch([prob], [dobs], [0] * batch)
+    fb.autotune(X[:batch])
+    f = np.empty(n)
+    for k in range(0, n, batch):
+        xb = X[k:k + batch]
+        if len(xb) < batch:                       # pad the last batch with copies of its first row
+            xb = np.concatenate([xb, np.repeat(xb[:1], batch - len(xb), axis=0)])
+        f[k:k + batch] = fb(xb).cpu().numpy()[:min(batch, n - k)]
+    return X, f
 
 
 def evals_to_reach(history, target):

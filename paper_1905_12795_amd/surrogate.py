@@ -198,31 +198,72 @@ class RandomRanker:
 
 
 class ScreenedEMPSO(EMPSO):
-    """EMPSO whose Eq. 1-2 move is chosen among K candidate draws per particle
-    by the surrogate. With K = 1 (or before `warmup` iterations) it is EMPSO.
+    """EMPSO whose moves, and optionally whose evaluations, are chosen by the
+    surrogate.
 
-    The draw order per iteration: K pairs (u1, u2) of [N][D] uniforms, then the
-    elitist-mutation draws as in EMPSO.
+    Every iteration each particle proposes K candidate moves (independent draws
+    of Eq. 1's u1, u2) and takes the one the surrogate ranks best, so N K
+    candidates are screened. With evaluate = M < N only the M particles whose
+    new positions rank best across the swarm go to the finite-difference
+    fitness; the others move without an evaluation (their personal bests
+    stand) and rank below every evaluated particle for the elitist mutation,
+    among themselves in the order of their predicted misfit. With M = N every
+    particle is evaluated. With K = 1 and M = N (or during the first `warmup`
+    iterations with M = N) it is EMPSO. The finite-difference fitness stays
+    the judge: personal and global bests change only on evaluated values.
+
+    Draw order per iteration: K pairs (u1, u2) of [N][D] uniforms, then the
+    elitist-mutation draws as in EMPSO; with M < N and an untrained surrogate
+    (iterations before `warmup`) a permutation of N picks the evaluated
+    particles at random.
     """
 
-    def __init__(self, lo, hi, n, surrogate, K=16, warmup=2, **kw):
+    def __init__(self, lo, hi, n, surrogate, K=16, warmup=2, evaluate=None, **kw):
         super().__init__(lo, hi, n, **kw)
         self.sur = surrogate
         self.K = int(K)
         self.warmup = int(warmup)
+        self.M = self.N if evaluate is None else int(evaluate)
+        if not 1 <= self.M <= self.N:
+            raise ValueError("evaluate must lie in [1, N]")
+        self.sel = None                      # particles evaluated at the current positions
+        self.pred = np.zeros(self.N)         # predicted scores of the current positions
         self.last_rank_corr = None
+
+    def _select(self):
+        """Choose the M particles to evaluate at the current positions."""
+        if self.M == self.N:
+            self.sel = np.arange(self.N)
+            return
+        if self.k < self.warmup:
+            self.sel = np.sort(self.rng.permutation(self.N)[:self.M])
+            self.pred = np.zeros(self.N)
+            return
+        self.pred = self.sur.predict(self.x)
+        self.sel = np.sort(np.argsort(self.pred, kind="stable")[:self.M])
+
+    def ask(self):
+        if self.sel is None:
+            self._select()
+        return self.x[self.sel]
 
     def tell(self, f):
         f = np.asarray(f, dtype=np.float64).copy()
+        if self.sel is None:
+            self._select()
+        if f.shape != (len(self.sel),):
+            raise ValueError("need %d fitness values" % len(self.sel))
         f[~np.isfinite(f)] = np.inf
-        self.sur.add(self.x, np.where(np.isfinite(f), f, np.float32(3e38)))
+        self.sur.add(self.x[self.sel], np.where(np.isfinite(f), f, np.float32(3e38)))
         self.sur.train()
-        if self.k + 1 < self.warmup or self.K <= 1:
+        if self.M == self.N and (self.k + 1 < self.warmup or self.K <= 1):
             return super().tell(f)
-        # bests (as in EMPSO.tell)
-        self.evaluations += self.N
-        better = f < self.fp
-        self.fp = np.where(better, f, self.fp)
+        fa = np.full(self.N, np.inf)
+        fa[self.sel] = f
+        # bests (as in EMPSO.tell), on the evaluated particles only
+        self.evaluations += len(self.sel)
+        better = fa < self.fp
+        self.fp = np.where(better, fa, self.fp)
         self.p = np.where(better[:, None], self.x, self.p)
         self.gi = int(np.argmin(self.fp))
         self.k += 1
@@ -236,18 +277,28 @@ class ScreenedEMPSO(EMPSO):
             cand_v.append(v)
             cand_x.append(np.minimum(np.maximum(self.x + v, self.lo), self.hi))
         cx = np.stack(cand_x)                       # [K][N][D]
-        pred = self.sur.predict(cx.reshape(-1, self.D)).reshape(self.K, self.N)
-        pick = np.argmin(pred, axis=0)
+        if self.K > 1 and self.k >= self.warmup:
+            pred = self.sur.predict(cx.reshape(-1, self.D)).reshape(self.K, self.N)
+            pick = np.argmin(pred, axis=0)
+        else:
+            pick = np.zeros(self.N, dtype=np.int64)
         x = cx[pick, np.arange(self.N)]
         v = np.stack(cand_v)[pick, np.arange(self.N)]
         if self.elitist and self.k >= self.em_start and self.nm > 0:
             ru = self.rng.random((self.nm, self.D))
             rn = self.rng.standard_normal((self.nm, self.D))
-            worst = np.argsort(-f, kind="stable")[:self.nm]
+            # worst first: unevaluated particles (by predicted score, highest
+            # first), then evaluated ones by fitness; ties in index order
+            evaluated = np.zeros(self.N, dtype=bool)
+            evaluated[self.sel] = True
+            key = np.where(evaluated, fa, np.inf)
+            worst = np.lexsort((np.arange(self.N), -np.where(evaluated, 0.0, self.pred), -key))[:self.nm]
             mut = np.where(ru < self.p_em, g + 0.1 * self.vr * rn, g)
             x[worst] = np.minimum(np.maximum(mut, self.lo), self.hi)
         self.x, self.v = x, v
+        self._select()
+        fin = f[np.isfinite(f)]
         self.history.append({"iteration": self.k, "best": float(self.fg),
-                             "mean": float(np.mean(f[np.isfinite(f)])) if np.any(np.isfinite(f)) else float("inf"),
+                             "mean": float(np.mean(fin)) if fin.size else float("inf"),
                              "median": float(np.median(f)), "evaluations": self.evaluations})
         return self.history[-1]
