@@ -15,6 +15,14 @@ HIPCC_FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     # no implicit multiply-add fusion: every kernel variant rounds identically
     "-ffp-contract=off",
+    # the stencil kernel's 10-step march loop must unroll completely (its
+    # register queues are indexed by the step within the block); with four
+    # forms of the update per step it exceeds the default size limit of
+    # forced unrolling
+    "-mllvm", "-pragma-unroll-threshold=100000",
+    # ... and a loop that a pragma asks to unroll but the compiler cannot
+    # fails the build instead of silently moving the queues to scratch
+    "-Werror=pass-failed",
     "-Wall", "-Wno-unused-function",
 ]
 

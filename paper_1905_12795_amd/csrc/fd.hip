@@ -89,6 +89,8 @@ struct empso_problem {
     float *d_wav = nullptr;    // [nt]
     float *d_az = nullptr;     // [Nz] a = d dt / 2 along z
     float *d_ax = nullptr;     // [Nx]
+    float *d_zoma = nullptr;   // [Nz] 1 - a_z
+    float *d_zinv = nullptr;   // [Nz] 1 / (1 + a_z) (the device's reciprocal)
     int *d_recmap = nullptr;   // [Nx] receiver index of a padded column or -1
     int *d_reccol = nullptr;   // [nrec]
     // node-to-grid interpolation tables (regular and layered node grids):
@@ -101,6 +103,16 @@ struct empso_problem {
     float *d_cu = nullptr;     // [levels][nx]
     float c0, cz[4], cx[4], wscale;
 };
+
+// Damping factors of the rows: 1 - a_z and the device reciprocal of 1 + a_z,
+// the values the stencil kernel's full damped form computes when a_x = 0.
+__global__ void k_zfactors(const float *__restrict__ az, int Nz, float *__restrict__ zoma, float *__restrict__ zinv) {
+    const int I = blockIdx.x * blockDim.x + threadIdx.x;
+    if (I < Nz) {
+        zoma[I] = 1.0f - az[I];
+        zinv[I] = __builtin_amdgcn_rcpf(1.0f + az[I]);
+    }
+}
 
 extern "C" const char *empso_status_string(int s) {
     switch (s) {
@@ -145,6 +157,8 @@ static void free_problem(empso_problem *p) {
     if (p->d_wav) (void)hipFree(p->d_wav);
     if (p->d_az) (void)hipFree(p->d_az);
     if (p->d_ax) (void)hipFree(p->d_ax);
+    if (p->d_zoma) (void)hipFree(p->d_zoma);
+    if (p->d_zinv) (void)hipFree(p->d_zinv);
     if (p->d_recmap) (void)hipFree(p->d_recmap);
     if (p->d_reccol) (void)hipFree(p->d_reccol);
     if (p->d_rowa) (void)hipFree(p->d_rowa);
@@ -359,12 +373,19 @@ extern "C" int empso_problem_create(const empso_geometry *gp, empso_problem **ou
     if (e == hipSuccess) e = hipMalloc(&p->d_wav, sizeof(float) * g.nt);
     if (e == hipSuccess) e = hipMalloc(&p->d_az, sizeof(float) * p->Nz);
     if (e == hipSuccess) e = hipMalloc(&p->d_ax, sizeof(float) * p->Nx);
+    if (e == hipSuccess) e = hipMalloc(&p->d_zoma, sizeof(float) * p->Nz);
+    if (e == hipSuccess) e = hipMalloc(&p->d_zinv, sizeof(float) * p->Nz);
     if (e == hipSuccess) e = hipMalloc(&p->d_recmap, sizeof(int) * p->Nx);
     if (e == hipSuccess) e = hipMalloc(&p->d_reccol, sizeof(int) * g.nrec);
     if (e == hipSuccess) e = hipMemcpy(p->d_wav, wav.data(), sizeof(float) * g.nt, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(p->d_az, az.data(), sizeof(float) * p->Nz, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(p->d_ax, ax.data(), sizeof(float) * p->Nx, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(p->d_recmap, recmap.data(), sizeof(int) * p->Nx, hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        k_zfactors<<<(p->Nz + 255) / 256, 256>>>(p->d_az, p->Nz, p->d_zoma, p->d_zinv);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
     if (e == hipSuccess)
         e = hipMemcpy(p->d_reccol, p->reccol.data(), sizeof(int) * g.nrec, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
@@ -422,6 +443,7 @@ struct RunDesc {
     double *acc;                // l2: [nrec] running sum of squared residuals;
                                 // trace-normalised: [3][nrec] sums of d^2, d o, o^2
     const float *wav, *az, *ax;
+    const float *zoma, *zinv;   // [Nz] row factors 1 - a_z, 1 / (1 + a_z)
     const int *recmap, *reccol;
     int Nz, Nx, S, nrec, recS, srcS, srcC, nt;
     int zlo, zhi;               // stored rows [zlo, zhi) have a_z = 0
@@ -647,14 +669,24 @@ __device__ __forceinline__ float from_lane_above(float v) {
 // Points outside the padded grid need no masking: C is zero there and so are
 // the incoming fields, so they stay exactly zero at every level.
 // Receiver samples of each level (u^{n+t-1} on the receiver row) are parked
-// in LDS and accumulated after the march by the owning lanes.
+// in LDS and accumulated after the march by the owning lanes; every step
+// parks its rows (an extra slot takes those off the receiver row), so the
+// step has no branch around the store.
+// The damped update d = (C (lap + f) + (1 - a) dp) / (1 + a), a = a_z + a_x,
+// is evaluated in the cheapest form that a step's rows and a tile's columns
+// allow: with a = 0 as d = C (lap + f) + dp; in a tile holding damped
+// columns, on rows with a_z = 0, from per-lane factors 1 - a_x and
+// 1 / (1 + a_x); on rows with a_z != 0 in any other tile, from the row
+// factors 1 - a_z and 1 / (1 + a_z) (tables built on the device with the
+// same reciprocal); otherwise in full. Each form is the full one with a
+// zero term, bit for bit, so the results do not depend on the tiling.
 template <int T, bool ISO>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(T < 3 ? 3 : 2))) void k_tb(const RunDesc *__restrict__ runs, const int4 *__restrict__ tiles,
                                             int ntiles, int n, int par) {
     constexpr int NS = kQueue;
     constexpr int FILL = 8 * (T - 1);               // march steps before the first owned row
     constexpr int TQ = T > 1 ? T - 1 : 1;
-    __shared__ float4 srec[4][T][64];
+    __shared__ float4 srec[4][T + 1][64];          // slot T: samples of rows off the receiver row
     const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
     const int wv = (int)(threadIdx.x >> 6);
     const int tix = __builtin_amdgcn_readfirstlane(lb * 4 + wv);
@@ -687,12 +719,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(T < 3 ? 3 :
     const int lcol = 4 * cc;                        // byte offset of the lane's columns in a row
     const int rowb = 4 * S;                         // bytes per stored row
 
-    float axk[4], srcm[4];
+    float axk[4], xoma[4], xinv[4], srcm[4];
     bool xdamp = false;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int J = J0 + k;
         axk[k] = (J >= 0 && J < R.Nx) ? gld(R.ax + J) : 0.0f;
+        xoma[k] = 1.0f - axk[k];                        // the factors of a = a_x (rows with a_z = 0)
+        xinv[k] = __builtin_amdgcn_rcpf(1.0f + axk[k]);
         xdamp |= axk[k] != 0.0f;
         srcm[k] = (c + k == R.srcC) ? 1.0f : 0.0f;     // this lane holds the source column
     }
@@ -715,11 +749,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(T < 3 ? 3 :
         for (int j = 0; j < NS; ++j) qu[l][j] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
 
-    // One march step: k = (step index) mod 10, known at compile time. The
-    // damped form is taken for the whole step when any of its T rows, or the
-    // tile, lies in the absorbing layer.
-    auto step = [&](const int k, const int r1, auto damp_tag) __attribute__((always_inline)) {
-        constexpr bool damped = decltype(damp_tag)::value;
+    // One march step: k = (step index) mod 10, known at compile time. Each
+    // step takes one form of the update for all its T levels, from the tile
+    // (does it hold a damped column) and the step (does any level's row lie
+    // in the z layer): undamped, per-lane x factors, row z factors from the
+    // tables, or the full damped form.
+    auto step = [&](const int k, const int r1, auto mode_tag) __attribute__((always_inline)) {
+        // 0: no damping; 1: a = a_x (per-lane factors); 2: a = a_z (row
+        // factors from the tables); 3: a = a_z + a_x in full
+        constexpr int mode = decltype(mode_tag)::value;
         q0[(k + 9) % NS] = bld4(F, uin + (r1 + 5) * rowb + lcol);
         float4 un = make_float4(0.f, 0.f, 0.f, 0.f), ue = un;
 #pragma unroll
@@ -749,7 +787,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(T < 3 ? 3 :
             const float pz4[4] = {p4.x, p4.y, p4.z, p4.w}, mz4[4] = {m4.x, m4.y, m4.z, m4.w};
             const float pvv[4] = {pv.x, pv.y, pv.z, pv.w};
             const float Cv[4] = {C4.x, C4.y, C4.z, C4.w};
-            const float azr = damped ? sld(R.az + min(max(r - kRing, 0), R.Nz - 1)) : 0.0f;
+            const int rz = min(max(r - kRing, 0), R.Nz - 1);
+            const float azr = (mode == 3) ? sld(R.az + rz) : 0.0f;
+            const float zo = (mode == 2) ? sld(R.zoma + rz) : 1.0f;
+            const float zi = (mode == 2) ? sld(R.zinv + rz) : 1.0f;
             const float fs = (r == R.srcS) ? fsrc[l] : 0.0f;   // wave-uniform
             float uo[4];
 #pragma unroll
@@ -778,20 +819,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(T < 3 ? 3 :
                 }
                 lap = fmaf(srcm[k2], fs, lap);
                 const float dp = u - pvv[k2];
-                // The damped form reduces bit for bit to the undamped one
-                // when a = 0 ((1-a) dp = dp, rcp(1) = 1), so a point's result
-                // does not depend on which branch its tile takes.
+                // Every form is the full damped one with some terms known to
+                // be zero, and reduces to it bit for bit there (a_z + 0 = a_z,
+                // 0 + a_x = a_x, (1-0) dp = dp, rcp(1) = 1), so a point's
+                // result does not depend on which form its tile and step take.
                 float d;
-                if constexpr (damped) {
+                if constexpr (mode == 0) {
+                    d = fmaf(Cv[k2], lap, dp);
+                } else if constexpr (mode == 1) {
+                    d = fmaf(Cv[k2], lap, xoma[k2] * dp) * xinv[k2];
+                } else if constexpr (mode == 2) {
+                    d = fmaf(Cv[k2], lap, zo * dp) * zi;
+                } else {
                     const float a = azr + axk[k2];
                     const float inv = __builtin_amdgcn_rcpf(1.0f + a);
                     d = fmaf(Cv[k2], lap, (1.0f - a) * dp) * inv;
-                } else {
-                    d = fmaf(Cv[k2], lap, dp);
                 }
                 uo[k2] = u + d;
             }
-            if (r == R.recS) srec[wv][l][lane] = ce;
+            srec[wv][(r == R.recS) ? l : T][lane] = ce;      // no branch inside the step
             un = make_float4(uo[0], uo[1], uo[2], uo[3]);
             ue = ce;
             if (l < T - 1) qu[l][(k + 8) % NS] = un;
@@ -804,10 +850,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(T < 3 ? 3 :
     };
 
     auto step_any = [&](const int k, const int r1) __attribute__((always_inline)) {
-        if (tile_xdamp || r1 - 4 * (T - 1) < R.zlo || r1 >= R.zhi)
-            step(k, r1, std::true_type{});
-        else
-            step(k, r1, std::false_type{});
+        const bool zrow = r1 - 4 * (T - 1) < R.zlo || r1 >= R.zhi;     // some level's row has a_z != 0
+        if (tile_xdamp) {
+            if (zrow)
+                step(k, r1, std::integral_constant<int, 3>{});
+            else
+                step(k, r1, std::integral_constant<int, 1>{});
+        } else {
+            if (zrow)
+                step(k, r1, std::integral_constant<int, 2>{});
+            else
+                step(k, r1, std::integral_constant<int, 0>{});
+        }
     };
     // march in blocks of NS steps: the first 8(T-1) steps only fill the
     // level queues and the last block may run past the tile; the stores of
@@ -1174,6 +1228,7 @@ static void build_header(Plan &pl, unsigned char *ws, const std::vector<const em
         d.obs = rs.obs; d.traces = rs.traces;
         d.acc = reinterpret_cast<double *>(ws + L.acc_of_run[r]);
         d.wav = p->d_wav; d.az = p->d_az; d.ax = p->d_ax; d.recmap = p->d_recmap; d.reccol = p->d_reccol;
+        d.zoma = p->d_zoma; d.zinv = p->d_zinv;
         d.Nz = p->Nz; d.Nx = p->Nx; d.S = p->S; d.nrec = p->g.nrec;
         d.recS = p->recI + kRing;
         d.zlo = p->zlo; d.zhi = p->zhi;
