@@ -241,6 +241,20 @@ size_t empso_traces_misfit_workspace_bytes(const empso_problem *prob, int32_t ns
 int empso_traces_misfit(const empso_problem *prob, const float *traces_d, const float *obs_d, int32_t nsh,
                         float *out_d, void *ws, size_t ws_bytes, empso_stream stream);
 
+/* empso_traces_misfit without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation). Its scratch (4 nsh nrec doubles) is a
+ * fixed array of the library on each GPU, held until the process ends, so
+ * the call allocates nothing; the result is bit-identical to
+ * empso_traces_misfit's. Limit: nsh * nrec <= EMPSO_NOALLOC_MAX_TRACES
+ * (ENOTSUP beyond it). Every call on a GPU uses that GPU's one scratch
+ * array: calls that overlap on one GPU (different streams, or host threads
+ * without ordering) race and give wrong results; calls ordered on one stream
+ * are safe. Nothing in the scratch needs clearing between calls. */
+#define EMPSO_NOALLOC_MAX_TRACES 262144
+int empso_traces_misfit_noalloc(const empso_problem *prob, const float *traces_d, const float *obs_d, int32_t nsh,
+                                float *out_d, empso_stream stream);
+
 /* Workspace bytes for empso_fitness_batch over np particles; particle p uses
  * problem probs[prob_of_particle[p]] (host array). 0 for an empty batch
  * (np = 0) and on invalid arguments. */

@@ -73,6 +73,7 @@ SIGNATURES = {
     "empso_misfit": (ctypes.c_int, [_vp, _vp, ctypes.c_int64, _vp, _vp, ctypes.c_size_t, _vp]),
     "empso_traces_misfit_workspace_bytes": (ctypes.c_size_t, [_vp, ctypes.c_int32]),
     "empso_traces_misfit": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int32, _vp, _vp, ctypes.c_size_t, _vp]),
+    "empso_traces_misfit_noalloc": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int32, _vp, _vp]),
     "empso_fitness_workspace_bytes": (ctypes.c_size_t, [_P(_vp), ctypes.c_int32, _P(ctypes.c_int32),
                                                         ctypes.c_int32]),
     "empso_fitness_batch": (ctypes.c_int, [_P(_vp), ctypes.c_int32, _P(_vp), _P(ctypes.c_int32),

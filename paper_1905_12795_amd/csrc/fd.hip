@@ -1478,6 +1478,45 @@ extern "C" int empso_traces_misfit(const empso_problem *p, const float *traces_d
                                  (hipStream_t)stream);
 }
 
+// Scratch of empso_traces_misfit_noalloc: one array per GPU for the life of
+// the process. In host code `scratch` names a host-side stand-in; kernels get
+// the device address that hipGetSymbolAddress returns for the current device.
+static constexpr size_t kScratchDoubles = (size_t)4 * EMPSO_NOALLOC_MAX_TRACES;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+static constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double *g_scratch_ptr[kMaxDevices];      // device address of scratch per device (NULL: not looked up)
+
+static int scratch_of_current_device(double **out) {
+    int dev = 0;
+    EMPSO_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) EMPSO_FAIL(EMPSO_ENOTSUP, "device %d beyond the %d this call supports", dev,
+                                                  kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            EMPSO_FAIL(EMPSO_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        g_scratch_ptr[dev] = static_cast<double *>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return EMPSO_OK;
+}
+
+extern "C" int empso_traces_misfit_noalloc(const empso_problem *p, const float *traces_d, const float *obs_d,
+                                           int32_t nsh, float *out_d, empso_stream stream) {
+    clear_error();
+    if (!p || !out_d || (nsh > 0 && (!traces_d || !obs_d))) EMPSO_FAIL(EMPSO_EINVAL, "NULL argument");
+    if (nsh < 0) EMPSO_FAIL(EMPSO_EINVAL, "nsh must be >= 0");
+    if ((int64_t)nsh * p->g.nrec > EMPSO_NOALLOC_MAX_TRACES)
+        EMPSO_FAIL(EMPSO_ENOTSUP, "nsh * nrec = %lld traces exceed the fixed scratch of %d traces",
+                   (long long)nsh * p->g.nrec, (int)EMPSO_NOALLOC_MAX_TRACES);
+    double *ws = nullptr;
+    const int rc = scratch_of_current_device(&ws);
+    if (rc) return rc;
+    return enqueue_traces_misfit(p, traces_d, obs_d, nsh, out_d, ws, (hipStream_t)stream);
+}
 
 static void forward_specs(const empso_problem *p, int32_t shot0, int32_t nsh, float *traces_d,
                           std::vector<const empso_problem *> &pp, std::vector<RunSpec> &runs) {

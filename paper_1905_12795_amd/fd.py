@@ -211,6 +211,18 @@ def traces_misfit(prob, traces, obs, out=None, ws=None):
     return out
 
 
+def traces_misfit_noalloc(prob, traces, obs, out):
+    """traces_misfit into a caller-given out [1] without any workspace: the
+    library's fixed per-GPU scratch (empso_traces_misfit_noalloc; calls that
+    overlap on one GPU race)."""
+    nsh = traces.shape[0] if traces.dim() == 3 else -1
+    _need(traces, torch.float32, (nsh, prob.nt, prob.nrec), "traces")
+    _need(obs, torch.float32, (nsh, prob.nt, prob.nrec), "obs")
+    _need(out, torch.float32, (1,), "out")
+    check(lib.empso_traces_misfit_noalloc(prob.handle, _ptr(traces), _ptr(obs), nsh, _ptr(out), _stream()))
+    return out
+
+
 class FitnessBatch:
     """Reusable fitness evaluation of a fixed set of particles over one or more problems.
 
