@@ -126,16 +126,18 @@ class EMPSO:
 
 
 def save_checkpoint(path, swarm):
-    """Swarm state (positions, velocities, bests, RNG state, log) in one .npz."""
+    """Swarm state (positions, velocities, bests, RNG state, log, and whatever
+    else a subclass's state_dict holds) in one .npz: arrays as arrays, the
+    rest as JSON text."""
     s = swarm.state_dict()
-    meta = json.dumps({"gi": s["gi"], "k": s["k"], "evaluations": s["evaluations"], "rng": s["rng"],
-                       "history": s["history"]})
-    np.savez(path, x=s["x"], v=s["v"], p=s["p"], fp=s["fp"], meta=np.frombuffer(meta.encode(), dtype=np.uint8))
+    arrays = {k: v for k, v in s.items() if isinstance(v, np.ndarray)}
+    meta = json.dumps({k: v for k, v in s.items() if not isinstance(v, np.ndarray)})
+    np.savez(path, meta=np.frombuffer(meta.encode(), dtype=np.uint8), **arrays)
 
 
 def load_checkpoint(path, swarm):
     """Restore a swarm saved by save_checkpoint (no pickles are loaded)."""
     d = np.load(path, allow_pickle=False)
     meta = json.loads(bytes(d["meta"]).decode())
-    swarm.load_state_dict({"x": d["x"], "v": d["v"], "p": d["p"], "fp": d["fp"], **meta})
+    swarm.load_state_dict({**{k: d[k] for k in d.files if k != "meta"}, **meta})
     return swarm

@@ -70,6 +70,21 @@ class MLP:
         self._ws = {}
         check(lib.empso_mlp_sync_bf16(self.D, self.H, _ptr(self.params), _ptr(self.wbf16), _stream()))
 
+    def state_dict(self):
+        """FP32 parameters, Adam moments and step count (host copies)."""
+        return {"params": self.params.cpu().numpy(), "m": self.m.cpu().numpy(), "v": self.v.cpu().numpy(),
+                "step": self.step}
+
+    def load_state_dict(self, st):
+        for name in ("params", "m", "v"):
+            t = getattr(self, name)
+            a = np.asarray(st[name], dtype=np.float32)
+            if a.shape != tuple(t.shape):
+                raise ValueError("%s has shape %s, want %s" % (name, a.shape, tuple(t.shape)))
+            t.copy_(torch.as_tensor(a))
+        self.step = int(st["step"])
+        check(lib.empso_mlp_sync_bf16(self.D, self.H, _ptr(self.params), _ptr(self.wbf16), _stream()))
+
     def _workspace(self, n):
         if n not in self._ws:
             nb = lib.empso_mlp_workspace_bytes(self.D, self.H, n)
@@ -168,6 +183,29 @@ class Surrogate:
                 loss = net.train_step(self.X, self.f, idx[m * per + k], self.mu, self.sigma, self.lr)
         return float(loss.item())
 
+    def state_dict(self):
+        """Everything a resumed search needs to continue bit for bit: every
+        network's state, the dataset, the target standardisation and the
+        mini-batch generator's state."""
+        return {"nets": [n.state_dict() for n in self.nets], "X": self.X[:self.count].cpu().numpy(),
+                "f": self.f[:self.count].cpu().numpy(), "logf": list(self.logf), "count": self.count,
+                "mu": self.mu, "sigma": self.sigma, "rng": self.rng.bit_generator.state}
+
+    def load_state_dict(self, st):
+        if len(st["nets"]) != len(self.nets):
+            raise ValueError("the state holds %d networks, this surrogate %d" % (len(st["nets"]), len(self.nets)))
+        for n, ns in zip(self.nets, st["nets"]):
+            n.load_state_dict(ns)
+        k = int(st["count"])
+        if k > self.X.shape[0]:
+            raise ValueError("dataset of %d rows exceeds the capacity %d" % (k, self.X.shape[0]))
+        self.X[:k] = torch.as_tensor(np.asarray(st["X"], np.float32), device=self.X.device)
+        self.f[:k] = torch.as_tensor(np.asarray(st["f"], np.float32), device=self.X.device)
+        self.count = k
+        self.logf = [float(x) for x in st["logf"]]
+        self.mu, self.sigma = float(st["mu"]), float(st["sigma"])
+        self.rng.bit_generator.state = st["rng"]
+
     def predict(self, X):
         """Host [n][D] -> host score [n]: the predicted standardised log-misfit
         (members' mean + kappa * spread for an ensemble)."""
@@ -229,6 +267,16 @@ class ScreenedEMPSO(EMPSO):
         self.sel = None                      # particles evaluated at the current positions
         self.pred = np.zeros(self.N)         # predicted scores of the current positions
         self.last_rank_corr = None
+
+    def state_dict(self):
+        st = super().state_dict()
+        st.update(sel=None if self.sel is None else self.sel.copy(), pred=self.pred.copy())
+        return st
+
+    def load_state_dict(self, st):
+        super().load_state_dict(st)
+        self.sel = None if st.get("sel") is None else np.asarray(st["sel"], dtype=np.int64)
+        self.pred = np.asarray(st["pred"], dtype=np.float64)
 
     def _select(self):
         """Choose the M particles to evaluate at the current positions."""
@@ -302,3 +350,29 @@ class ScreenedEMPSO(EMPSO):
                              "mean": float(np.mean(fin)) if fin.size else float("inf"),
                              "median": float(np.median(f)), "evaluations": self.evaluations})
         return self.history[-1]
+
+
+def save_surrogate(path, sur):
+    """A surrogate's state (Surrogate.state_dict) in one .npz: arrays as arrays,
+    the rest as JSON text; no pickles."""
+    import json
+    st = sur.state_dict()
+    arrays = {"X": st["X"], "f": st["f"], "logf": np.asarray(st["logf"], dtype=np.float64)}
+    for k, ns in enumerate(st["nets"]):
+        for name in ("params", "m", "v"):
+            arrays["net%d_%s" % (k, name)] = ns[name]
+    meta = {"count": st["count"], "mu": st["mu"], "sigma": st["sigma"], "rng": st["rng"],
+            "steps": [ns["step"] for ns in st["nets"]]}
+    np.savez(path, meta=np.frombuffer(json.dumps(meta).encode(), dtype=np.uint8), **arrays)
+
+
+def load_surrogate(path, sur):
+    """Restore a surrogate saved by save_surrogate (no pickles are loaded)."""
+    import json
+    d = np.load(path, allow_pickle=False)
+    meta = json.loads(bytes(d["meta"]).decode())
+    nets = [{"params": d["net%d_params" % k], "m": d["net%d_m" % k], "v": d["net%d_v" % k], "step": step}
+            for k, step in enumerate(meta["steps"])]
+    sur.load_state_dict({"nets": nets, "X": d["X"], "f": d["f"], "logf": d["logf"].tolist(),
+                         "count": meta["count"], "mu": meta["mu"], "sigma": meta["sigma"], "rng": meta["rng"]})
+    return sur

@@ -87,3 +87,21 @@ def test_random_ranker_screen_runs_and_counts():
         x = sw.ask()
         sw.tell(np.sum((x - c) ** 2, axis=1))
     assert sw.evaluations == 30 and np.isfinite(sw.fg)
+
+
+def test_screened_swarm_checkpoint_resumes_bitwise(tmp_path):
+    lo, hi, c = _box(seed=4)
+    kw = dict(K=3, warmup=0, evaluate=6, gen=12, seed=13)
+
+    def f(x):
+        return np.sum((x - c) ** 2, axis=1)
+
+    a = ScreenedEMPSO(lo, hi, 14, _Exact(c), **kw)
+    for _ in range(4):
+        a.tell(f(a.ask()))
+    pso.save_checkpoint(str(tmp_path / "s.npz"), a)
+    b = pso.load_checkpoint(str(tmp_path / "s.npz"), ScreenedEMPSO(lo, hi, 14, _Exact(c), **kw))
+    for _ in range(5):
+        ra, rb = a.tell(f(a.ask())), b.tell(f(b.ask()))
+        assert ra == rb
+    assert np.array_equal(a.x, b.x) and np.array_equal(a.sel, b.sel) and np.array_equal(a.p, b.p)
