@@ -188,6 +188,24 @@ def surrogate_paired(workload, iters, seeds, N, K, M, pretrain_path, pretrain_n,
     _emit(summ)
 
 
+def pretrain(workload, total, start, stop, out):
+    """Rows [start, stop) of the seeded uniform draw of `total` particles,
+    evaluated by the FD fitness, saved as (X, f) to `out` (.npz)."""
+    g = config(workload)
+    prob = fd.Problem(g)
+    dobs = search.observed_for(g, prob, true_model(g))
+    t0 = time.perf_counter()
+    def progress(done, n):
+        if done % 1280 == 0 or done == n:
+            _emit({"stage": "pretraining pairs", "done": done, "of": n, "seconds": time.perf_counter() - t0})
+
+    X, f = search.pretrain_pairs(prob, dobs, g["node_lo"], g["node_hi"], total, seed=1000, start=start, stop=stop,
+                                 progress=progress)
+    np.savez(out, X=X, f=f, start=start, stop=stop, total=total)
+    _emit({"stage": "pretraining pairs", "rows": [start, stop], "seconds": time.perf_counter() - t0,
+           "evals_per_s": len(f) / (time.perf_counter() - t0), "out": out})
+
+
 def fwi_bands(g, prob, truth, bands):
     """Stages of a multiscale FWI on data from the workload's observing source:
     per band (f0, f_pass, f_stop, iterations), a problem with a Ricker source
@@ -342,6 +360,12 @@ def main():
     sp.add_argument("--pretrain-n", type=int, default=20000)
     sp.add_argument("--pretrain-steps", type=int, default=3000)
     sp.add_argument("--log", default=None)
+    pt = sub.add_parser("pretrain")
+    pt.add_argument("--workload", default="realistic", choices=["mini", "realistic"])
+    pt.add_argument("--total", type=int, default=20000)
+    pt.add_argument("--start", type=int, default=0)
+    pt.add_argument("--stop", type=int, default=None)
+    pt.add_argument("--out", required=True)
     f = sub.add_parser("fwi")
     f.add_argument("--workload", default="realistic", choices=["realistic", "irregular", "crime_free"])
     f.add_argument("--search-iters", type=int, default=15)
@@ -370,6 +394,8 @@ def main():
         mlp_timing(a.reps)
     elif a.cmd == "bandwidth":
         bandwidth(a.mib, a.reps)
+    elif a.cmd == "pretrain":
+        pretrain(a.workload, a.total, a.start, a.stop if a.stop is not None else a.total, a.out)
     elif a.cmd == "surrogate-paired":
         surrogate_paired(a.workload, a.iters, [int(x) for x in a.seeds.split(",")], a.particles, a.K, a.evaluate,
                          a.pretrain, a.pretrain_n, a.pretrain_steps, a.log)

@@ -163,12 +163,15 @@ def run(geom, dobs, prob, iterations, mode="plain", seed=0, K=16, warmup=2, sur_
     return out
 
 
-def pretrain_pairs(prob, dobs, lo, hi, n, seed, batch=128):
-    """(X [n][D], fitness [n]) of n particles drawn uniformly in the search box
-    (seeded), evaluated by the FD fitness in batches: the data a surrogate
-    can be trained on before a search."""
+def pretrain_pairs(prob, dobs, lo, hi, n, seed, batch=128, start=0, stop=None, progress=None):
+    """(X, fitness) of particles drawn uniformly in the search box (n of them,
+    seeded), evaluated by the FD fitness in batches: the data a surrogate can
+    be trained on before a search. start/stop evaluate the rows [start, stop)
+    of the same draw only, so that the set can be built in parts.
+    progress(done, total), if given, is called after each batch."""
     from workloads.models import uniform_particles
-    X = uniform_particles(n, lo, hi, seed)
+    X = uniform_particles(n, lo, hi, seed)[start:stop]
+    n = len(X)
     fb = fd.FitnessBatch([prob], [dobs], [0] * batch)
     fb.autotune(X[:batch])
     f = np.empty(n)
@@ -177,6 +180,8 @@ def pretrain_pairs(prob, dobs, lo, hi, n, seed, batch=128):
         if len(xb) < batch:                       # pad the last batch with copies of its first row
             xb = np.concatenate([xb, np.repeat(xb[:1], batch - len(xb), axis=0)])
         f[k:k + batch] = fb(xb).cpu().numpy()[:min(batch, n - k)]
+        if progress:
+            progress(min(k + batch, n), n)
     return X, f
 
 
