@@ -357,7 +357,12 @@ int empso_time_tuning(const empso_problem *const *probs, int32_t nprob, const fl
  * Checkpointing: (u^n, u^{n-1}) are kept every K = checkpoint_every steps
  * (0: K = ceil(sqrt(2 (nt - 1)))), and each segment is recomputed during the
  * backward pass: about two forward passes and one adjoint pass of work, and
- * K + 7 + 2 ceil((nt - 1)/K) fields per shot of memory. The same pass can
+ * K + 8 + 2 ceil((nt - 1)/K) fields per shot of memory. K >= nt - 1 keeps
+ * every time level of one forward pass instead (one forward and one adjoint
+ * pass; nt + 9 fields per shot, e.g. 234 GB for 16 shots of 381 x 1001 points
+ * over 8114 steps). The adjoint advances up to three time steps per launch
+ * unless the illumination is requested, which the single-step adjoint
+ * accumulates; both give the same gradient to FP32 rounding. The same pass can
  * return the source illumination sum_s sum_{n>=1} u_s^n(x)^2, folded the same
  * way, the usual diagonal scaling (pseudo-Hessian) of the gradient.
  * ------------------------------------------------------------------------ */

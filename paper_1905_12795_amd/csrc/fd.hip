@@ -1972,16 +1972,18 @@ struct GradShared {
 };
 
 // Field slots of a run: 0 .. K+1 segment levels (the forward pass uses 0..2
-// as a ring), K+2 .. K+4 adjoint ring, K+5 gradient accumulator, K+6
-// illumination accumulator, then two per checkpoint.
+// as a ring), K+2 .. K+5 the adjoint's four contiguous fields (two pairs for
+// the blocked adjoint, a ring of three for the single-step one), K+6
+// gradient accumulator, K+7 illumination accumulator, then two per checkpoint.
 struct GradSlots {
     int K, ncheck;
     int seg(int i) const { return i; }
+    int adjp() const { return K + 2; }
     int adj(int k) const { return K + 2 + ((k % 3) + 3) % 3; }
-    int gacc() const { return K + 5; }
-    int illum() const { return K + 6; }
-    int ck(int j, int which) const { return K + 7 + 2 * j + which; }
-    int total() const { return K + 7 + 2 * ncheck; }
+    int gacc() const { return K + 6; }
+    int illum() const { return K + 7; }
+    int ck(int j, int which) const { return K + 8 + 2 * j + which; }
+    int total() const { return K + 8 + 2 * ncheck; }
 };
 
 static int grad_interval(const empso_problem *p, int K) {
@@ -2003,6 +2005,8 @@ static int grad_interval(const empso_problem *p, int K) {
 // Thread (x, y) of block (bx, by, run) updates columns 4 (64 bx + x) .. +3 of
 // padded row kGRows by + y.
 static constexpr int kGRows = 4;     // rows per block of k_gstep
+static constexpr int kAdjT = 3;      // adjoint steps per launch of k_tba
+static constexpr int kAdjBz = 20;    // its tile height (16 shots fill the GPU only with short strips)
 template <bool ADJ, bool ISO>
 __global__ __launch_bounds__(64 * kGRows) void k_gstep(const GradRun *__restrict__ runs, const GradShared sh, int cur,
                                                int prev, int out, float fsrc, int k, int uk, int gacc, int illum,
@@ -2096,6 +2100,248 @@ __global__ __launch_bounds__(64 * kGRows) void k_gstep(const GradRun *__restrict
     }
 }
 
+// Adjoint of one run (shot) for the temporally blocked adjoint kernel.
+struct AdjDesc {
+    float *psi;                 // four contiguous fields; pair p holds (psi^{k+1}, psi^{k+2}) in fields p, 2 + p
+    const float *C;             // coefficient field
+    const float *seg;           // segment levels: u^m in field m - b + 1, gfs floats apart
+    float *g;                   // imaging sum over m of u^m (Lap psi^{m+1} + r^m)
+    const float *obs;           // [nt][nrec]
+    double *acc;                // l2: [nrec] sums of squared residuals
+    const float *ab;            // trace-normalised: [3][nrec] adjoint-source factors a, b, 1/sd; else NULL
+    const float *ax, *az, *zoma, *zinv;
+    const int *recmap;
+    size_t gfs;
+    int Nz, Nx, S, nrec, recS, zlo, zhi;
+    unsigned fbytes;
+    float cz1, cz2, cz3, cz4, cx1, cx2, cx3, cx4;
+};
+
+// T adjoint steps k, k-1, .., k-T+1 of every tile, all levels in registers:
+// the same march as the fitness kernel k_tb with psi in the role of u, level
+// l computing psi^{k-l} from psi^{k-l+1} and psi^{k-l+2}, and the adjoint
+// source r^{k-l} (the residual at the receivers, or the trace-normalised
+// misfit's derivative) added to the Laplacian on the receiver row in place of
+// the Ricker source. The imaging sum takes u^{k-l} L at every point, with L =
+// Lap psi^{k-l+1} + r^{k-l} the quantity the update multiplies by C: the
+// adjoint recursion gives (1+a)(psi^m - psi^{m+1}) - (1-a)(psi^{m+1} - psi^{m+2})
+// = C L exactly, so the sum is dJ/dC times C (dJ/dv = 2 sum / v). A row's T
+// terms are added by the levels in time order (level 0 starts from the sum
+// read from HBM); between levels the partial sums wait in an LDS ring of 10
+// rows indexed by the step within the 10-step block, so every ring address is
+// known at compile time (4 (T - 1) < 10). The residuals of the T levels at
+// the receiver row are formed before the march and parked in LDS; the tile
+// that owns the receiver row adds the squared l2 residuals to the misfit.
+// u^{k-l} comes from the segment's stored levels. Stores, damping forms and
+// the zero ring work as in k_tb.
+template <int T, bool ISO>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_tba(const AdjDesc *__restrict__ descs,
+        const int4 *__restrict__ tiles, int ntiles, int k, int b, int par) {
+    constexpr int NS = kQueue;
+    constexpr int FILL = 8 * (T - 1);
+    constexpr int TQ = T > 1 ? T - 1 : 1;
+    static_assert(4 * (T - 1) < NS, "the imaging ring holds 10 rows");
+    __shared__ float4 sres[4][T + 1][64];
+    __shared__ float4 sg[4][NS][64];
+    const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
+    const int wv = (int)(threadIdx.x >> 6);
+    const int tix = __builtin_amdgcn_readfirstlane(lb * 4 + wv);
+    if (tix >= ntiles) return;
+    const int lane = threadIdx.x & 63;
+    const int4 t = tiles[tix];
+    const AdjDesc R = descs[t.x];
+    const int S = R.S;
+    const int bot = R.Nz + kRing;
+    const rsrc_t F = make_rsrc(R.psi, 4u * R.fbytes);
+    const int fb = (int)R.fbytes;
+    const int uin = par ? fb : 0, vin = par ? 3 * fb : 2 * fb;
+    const int uout = par ? 0 : fb, vout = par ? 2 * fb : 3 * fb;
+    const rsrc_t Cf = make_rsrc(R.C, R.fbytes);
+    const rsrc_t Gf = make_rsrc(R.g, R.fbytes);
+    rsrc_t Uf[T];
+#pragma unroll
+    for (int l = 0; l < T; ++l) Uf[l] = make_rsrc(R.seg + (size_t)(k - l - b + 1) * R.gfs, R.fbytes);
+    const int c = t.z + 4 * lane;
+    const int cc = min(c, S - 4);
+    const int J0 = c - kRing;
+    const bool own = (lane >= T) && (lane < 64 - T);
+    const int s0 = t.y;
+    const int s1 = min(t.w, bot);
+    const int lcol = 4 * cc;
+    const int rowb = 4 * S;
+
+    float axk[4], xoma[4], xinv[4];
+    bool xdamp = false;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int J = J0 + q;
+        axk[q] = (J >= 0 && J < R.Nx) ? gld(R.ax + J) : 0.0f;
+        xoma[q] = 1.0f - axk[q];
+        xinv[q] = __builtin_amdgcn_rcpf(1.0f + axk[q]);
+        xdamp |= axk[q] != 0.0f;
+    }
+    const bool tile_xdamp = __any(xdamp);
+
+    // adjoint sources of the T levels on the receiver row
+    const bool rec_owner = own && R.recS >= s0 && R.recS < s1;
+    sres[wv][T][lane] = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (int l = 0; l < T; ++l) {
+        const int m = k - l;
+        const float4 u4 = bld4(Uf[l], R.recS * rowb + lcol);
+        const float uu[4] = {u4.x, u4.y, u4.z, u4.w};
+        float rr[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int J = J0 + q;
+            rr[q] = 0.0f;
+            const int r = (J >= 0 && J < R.Nx) ? gld(R.recmap + J) : -1;
+            if (r >= 0) {
+                const float ob = gld(R.obs + (size_t)m * R.nrec + r);
+                if (R.ab) {
+                    rr[q] = fmaf(gld(R.ab + r), uu[q], -gld(R.ab + R.nrec + r) * ob) * gld(R.ab + 2 * R.nrec + r);
+                } else {
+                    rr[q] = uu[q] - ob;
+                    if (rec_owner) gst(R.acc + r, gld(R.acc + r) + (double)rr[q] * (double)rr[q]);
+                }
+            }
+        }
+        sres[wv][l][lane] = make_float4(rr[0], rr[1], rr[2], rr[3]);
+    }
+
+    const int rs = s0 - 4 * (T - 1);
+    float4 q0[NS], qu[TQ][NS], vq, cq[T], ukq[T], gq;
+#pragma unroll
+    for (int j = 0; j < 9; ++j) q0[j] = bld4(F, uin + (rs - 4 + j) * rowb + lcol);
+    vq = bld4(F, vin + rs * rowb + lcol);
+#pragma unroll
+    for (int l = 0; l < T; ++l) {
+        cq[l] = bld4(Cf, (rs - 4 * l) * rowb + lcol);
+        ukq[l] = bld4(Uf[l], (rs - 4 * l) * rowb + lcol);
+    }
+    gq = bld4(Gf, rs * rowb + lcol);
+#pragma unroll
+    for (int l = 0; l < TQ; ++l) {
+#pragma unroll
+        for (int j = 0; j < NS; ++j) qu[l][j] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+
+    auto step = [&](const int kk, const int r1, auto mode_tag) __attribute__((always_inline)) {
+        constexpr int mode = decltype(mode_tag)::value;
+        q0[(kk + 9) % NS] = bld4(F, uin + (r1 + 5) * rowb + lcol);
+        float4 un = make_float4(0.f, 0.f, 0.f, 0.f), ue = un, gout = un;
+#pragma unroll
+        for (int l = 0; l < T; ++l) {
+            const float4 *src = (l == 0) ? q0 : qu[l > 0 ? l - 1 : 0];
+            const float4 ce = src[(kk + 4) % NS];
+            const float4 p1 = src[(kk + 3) % NS], m1 = src[(kk + 5) % NS];
+            const float4 p2 = src[(kk + 2) % NS], m2 = src[(kk + 6) % NS];
+            const float4 p3 = src[(kk + 1) % NS], m3 = src[(kk + 7) % NS];
+            const float4 p4 = src[(kk + 0) % NS], m4 = src[(kk + 8) % NS];
+            const float4 pv = (l == 0) ? vq : ((l == 1) ? q0 : qu[l > 1 ? l - 2 : 0])[kk % NS];
+            const float4 C4 = cq[l];
+            const float4 U4 = ukq[l];
+            const int r = r1 - 4 * l;
+            cq[l] = bld4(Cf, (r + 1) * rowb + lcol);
+            ukq[l] = bld4(Uf[l], (r + 1) * rowb + lcol);
+            if (l == 0) vq = bld4(F, vin + (r1 + 1) * rowb + lcol);
+            const float v[12] = {from_lane_below(ce.x), from_lane_below(ce.y),
+                                 from_lane_below(ce.z), from_lane_below(ce.w),
+                                 ce.x, ce.y, ce.z, ce.w,
+                                 from_lane_above(ce.x), from_lane_above(ce.y),
+                                 from_lane_above(ce.z), from_lane_above(ce.w)};
+            const float pz1[4] = {p1.x, p1.y, p1.z, p1.w}, mz1[4] = {m1.x, m1.y, m1.z, m1.w};
+            const float pz2[4] = {p2.x, p2.y, p2.z, p2.w}, mz2[4] = {m2.x, m2.y, m2.z, m2.w};
+            const float pz3[4] = {p3.x, p3.y, p3.z, p3.w}, mz3[4] = {m3.x, m3.y, m3.z, m3.w};
+            const float pz4[4] = {p4.x, p4.y, p4.z, p4.w}, mz4[4] = {m4.x, m4.y, m4.z, m4.w};
+            const float pvv[4] = {pv.x, pv.y, pv.z, pv.w};
+            const float Cv[4] = {C4.x, C4.y, C4.z, C4.w};
+            const float Uv[4] = {U4.x, U4.y, U4.z, U4.w};
+            const int rz = min(max(r - kRing, 0), R.Nz - 1);
+            const float azr = (mode == 3) ? sld(R.az + rz) : 0.0f;
+            const float zo = (mode == 2) ? sld(R.zoma + rz) : 1.0f;
+            const float zi = (mode == 2) ? sld(R.zinv + rz) : 1.0f;
+            const float4 rs4 = sres[wv][(r == R.recS) ? l : T][lane];
+            const float rsv[4] = {rs4.x, rs4.y, rs4.z, rs4.w};
+            // imaging partial sum of this row: from HBM for the first level,
+            // else from the ring slot the previous level left it in
+            const float4 gp = (l == 0) ? gq : sg[wv][((kk - 4 * l) % NS + NS) % NS][lane];
+            const float gpv[4] = {gp.x, gp.y, gp.z, gp.w};
+            float uo[4], go[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float u = v[4 + q];
+                float lap;
+                if (ISO) {
+                    lap = R.cz4 * fmaf(-4.0f, u, (pz4[q] + mz4[q]) + (v[0 + q] + v[8 + q]));
+                    lap = fmaf(R.cz3, fmaf(-4.0f, u, (pz3[q] + mz3[q]) + (v[1 + q] + v[7 + q])), lap);
+                    lap = fmaf(R.cz2, fmaf(-4.0f, u, (pz2[q] + mz2[q]) + (v[2 + q] + v[6 + q])), lap);
+                    lap = fmaf(R.cz1, fmaf(-4.0f, u, (pz1[q] + mz1[q]) + (v[3 + q] + v[5 + q])), lap);
+                } else {
+                    lap = R.cz4 * fmaf(-2.0f, u, pz4[q] + mz4[q]);
+                    lap = fmaf(R.cz3, fmaf(-2.0f, u, pz3[q] + mz3[q]), lap);
+                    lap = fmaf(R.cz2, fmaf(-2.0f, u, pz2[q] + mz2[q]), lap);
+                    lap = fmaf(R.cz1, fmaf(-2.0f, u, pz1[q] + mz1[q]), lap);
+                    lap = fmaf(R.cx4, fmaf(-2.0f, u, v[0 + q] + v[8 + q]), lap);
+                    lap = fmaf(R.cx3, fmaf(-2.0f, u, v[1 + q] + v[7 + q]), lap);
+                    lap = fmaf(R.cx2, fmaf(-2.0f, u, v[2 + q] + v[6 + q]), lap);
+                    lap = fmaf(R.cx1, fmaf(-2.0f, u, v[3 + q] + v[5 + q]), lap);
+                }
+                lap += rsv[q];
+                const float dp = u - pvv[q];
+                float d;
+                if constexpr (mode == 0) {
+                    d = fmaf(Cv[q], lap, dp);
+                } else if constexpr (mode == 1) {
+                    d = fmaf(Cv[q], lap, xoma[q] * dp) * xinv[q];
+                } else if constexpr (mode == 2) {
+                    d = fmaf(Cv[q], lap, zo * dp) * zi;
+                } else {
+                    const float a = azr + axk[q];
+                    const float inv = __builtin_amdgcn_rcpf(1.0f + a);
+                    d = fmaf(Cv[q], lap, (1.0f - a) * dp) * inv;
+                }
+                uo[q] = u + d;
+                go[q] = fmaf(Uv[q], lap, gpv[q]);
+            }
+            const float4 g4 = make_float4(go[0], go[1], go[2], go[3]);
+            if (l < T - 1)
+                sg[wv][((kk - 4 * l) % NS + NS) % NS][lane] = g4;
+            else
+                gout = g4;
+            if (l == 0) gq = bld4(Gf, (r1 + 1) * rowb + lcol);
+            un = make_float4(uo[0], uo[1], uo[2], uo[3]);
+            ue = ce;
+            if (l < T - 1) qu[l][(kk + 8) % NS] = un;
+        }
+        const int rT = r1 - 4 * (T - 1);
+        const bool ok = own && (rT >= s0) && (rT < s1);
+        const int o = rT * rowb + lcol;
+        bst4(F, ok ? uout + o : kDrop, un);
+        bst4(F, ok ? vout + o : kDrop, ue);
+        bst4(Gf, ok ? o : kDrop, gout);
+    };
+    auto step_any = [&](const int kk, const int r1) __attribute__((always_inline)) {
+        const bool zrow = r1 - 4 * (T - 1) < R.zlo || r1 >= R.zhi;
+        if (tile_xdamp) {
+            if (zrow)
+                step(kk, r1, std::integral_constant<int, 3>{});
+            else
+                step(kk, r1, std::integral_constant<int, 1>{});
+        } else {
+            if (zrow)
+                step(kk, r1, std::integral_constant<int, 2>{});
+            else
+                step(kk, r1, std::integral_constant<int, 0>{});
+        }
+    };
+    const int nit = FILL + (s1 - s0);
+    for (int j = 0; j < nit; j += NS) {
+#pragma unroll
+        for (int kk = 0; kk < NS; ++kk) step_any(kk, rs + j + kk);
+    }
+}
+
 __global__ void k_gcopy(const GradRun *__restrict__ runs, size_t gfs, int src, int dst) {
     const GradRun R = runs[blockIdx.y];
     const float4 *a = reinterpret_cast<const float4 *>(R.fields + (size_t)src * gfs);
@@ -2106,9 +2352,9 @@ __global__ void k_gcopy(const GradRun *__restrict__ runs, size_t gfs, int src, i
 
 // Physical gradient: each physical point gathers the padded points that copy
 // it (its own, plus the absorbing-layer strip or corner beyond an edge), over
-// all runs in a fixed order, times 2 / (v^3 dt^2).
+// all runs in a fixed order, times 2 / (v^3 dt^2) or 2 / v (by_L).
 __global__ void k_gfold(const GradRun *__restrict__ runs, int nruns, const GradShared sh, int gacc, const float *vp,
-                        int nz, int nx, int nbl, double dt, float *grad, float *illum) {
+                        int nz, int nx, int nbl, double dt, int by_L, float *grad, float *illum) {
     const int64_t n = (int64_t)nz * nx;
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
         const int i = (int)(q / nx), j = (int)(q - (int64_t)i * nx);
@@ -2125,7 +2371,9 @@ __global__ void k_gfold(const GradRun *__restrict__ runs, int nruns, const GradS
                 }
         }
         const double v = vp[q];
-        grad[q] = (float)(sum * 2.0 / (v * v * v * dt * dt));
+        // the accumulator holds dJ/dC times C^2 (single-step adjoint) or times
+        // C (blocked adjoint); dJ/dv = dJ/dC 2 v dt^2 with C = (v dt)^2
+        grad[q] = (float)(by_L ? sum * 2.0 / v : sum * 2.0 / (v * v * v * dt * dt));
         if (illum) illum[q] = (float)ill;
     }
 }
@@ -2234,7 +2482,8 @@ __global__ __launch_bounds__(256) void k_gmisfit(const GradRun *__restrict__ run
 
 struct GradLayout {
     GradSlots sl;
-    size_t fb, runs_off, cd_off, acc_off, tsum_off, ab_off, C_off, fields_off, total;
+    size_t fb, runs_off, cd_off, adj_off, tiles_off, tiles1_off, acc_off, tsum_off, ab_off, C_off, fields_off, total;
+    int tile_cap;               // tile-table entries (all shots) for any tuning
 };
 
 static GradLayout grad_layout(const empso_problem *p, int K) {
@@ -2247,6 +2496,10 @@ static GradLayout grad_layout(const empso_problem *p, int K) {
     const int ns = p->g.nshots;
     L.runs_off = take(sizeof(GradRun) * ns);
     L.cd_off = take(sizeof(CoefDesc));
+    L.adj_off = take(sizeof(AdjDesc) * ns);
+    L.tile_cap = tile_capacity(p) * ns;
+    L.tiles_off = take(sizeof(int4) * (size_t)L.tile_cap);
+    L.tiles1_off = take(sizeof(int4) * (size_t)L.tile_cap);
     L.acc_off = take(sizeof(double) * (size_t)ns * p->g.nrec);
     const bool norm = p->g.misfit == EMPSO_MISFIT_TRACE_NORMALISED;
     L.tsum_off = take(norm ? sizeof(double) * (3 * (size_t)p->g.nrec + 2) * ns : 0);
@@ -2344,6 +2597,62 @@ extern "C" int empso_gradient(const empso_problem *p, const float *vp_d, const f
     };
     auto copy = [&](int src, int dst) { k_gcopy<<<dim3(cblocks, ns), 256, 0, st>>>(runs, gfs, src, dst); };
 
+    // The blocked adjoint (k_tba, T adjoint steps per launch) unless the
+    // illumination is asked for, which the single-step adjoint accumulates.
+    const bool blocked = illum_d == nullptr;
+    const int Ta = kAdjT, bza = kAdjBz;
+    AdjDesc *adjd = reinterpret_cast<AdjDesc *>(w + L.adj_off);
+    int4 *tdA = reinterpret_cast<int4 *>(w + L.tiles_off), *tdA1 = reinterpret_cast<int4 *>(w + L.tiles1_off);
+    int ntA = 0, ntA1 = 0;
+    if (blocked) {
+        std::vector<AdjDesc> ha(ns);
+        for (int s = 0; s < ns; ++s) {
+            AdjDesc &a = ha[s];
+            a.psi = hr[s].fields + (size_t)sl.adjp() * gfs;
+            a.C = sh.C;
+            a.seg = hr[s].fields;
+            a.g = hr[s].fields + (size_t)sl.gacc() * gfs;
+            a.obs = hr[s].obs;
+            a.acc = hr[s].acc;
+            a.ab = hr[s].ab;
+            a.ax = p->d_ax; a.az = p->d_az; a.zoma = p->d_zoma; a.zinv = p->d_zinv;
+            a.recmap = p->d_recmap;
+            a.gfs = gfs;
+            a.Nz = p->Nz; a.Nx = p->Nx; a.S = p->S; a.nrec = p->g.nrec; a.recS = p->recI + kRing;
+            a.zlo = p->zlo; a.zhi = p->zhi;
+            a.fbytes = (unsigned)L.fb;
+            a.cz1 = p->cz[0]; a.cz2 = p->cz[1]; a.cz3 = p->cz[2]; a.cz4 = p->cz[3];
+            a.cx1 = p->cx[0]; a.cx2 = p->cx[1]; a.cx3 = p->cx[2]; a.cx4 = p->cx[3];
+        }
+        std::vector<const empso_problem *> pp(1, p);
+        std::vector<RunSpec> rsp;
+        for (int s = 0; s < ns; ++s) rsp.push_back(RunSpec{p, 0, s, nullptr, nullptr});
+        std::vector<int4> htA(L.tile_cap), htA1(L.tile_cap);
+        fill_tiles(htA.data(), pp, rsp, bza, Ta);
+        fill_tiles(htA1.data(), pp, rsp, kTailBz, 1);
+        ntA = tiles_of(p, bza, Ta) * ns;
+        ntA1 = tiles_of(p, kTailBz, 1) * ns;
+        EMPSO_HIP(hipMemcpyAsync(adjd, ha.data(), sizeof(AdjDesc) * ns, hipMemcpyHostToDevice, st));
+        EMPSO_HIP(hipMemcpyAsync(tdA, htA.data(), sizeof(int4) * htA.size(), hipMemcpyHostToDevice, st));
+        EMPSO_HIP(hipMemcpyAsync(tdA1, htA1.data(), sizeof(int4) * htA1.size(), hipMemcpyHostToDevice, st));
+        EMPSO_HIP(hipStreamSynchronize(st));        // the host tables may go once the copies are done
+    }
+    auto launch_adj = [&](int T, int k, int b, int par) {
+        const int4 *tt = T == 1 ? tdA1 : tdA;
+        const int n_t = T == 1 ? ntA1 : ntA;
+        int blocks = (n_t + 3) / 4;
+        blocks = (blocks + 7) / 8 * 8;
+#define EMPSO_TBA_CASE(TT)                                                                           \
+        if (T == TT) {                                                                                \
+            if (iso)                                                                                  \
+                k_tba<TT, true><<<blocks, 256, 0, st>>>(adjd, tt, n_t, k, b, par);                    \
+            else                                                                                      \
+                k_tba<TT, false><<<blocks, 256, 0, st>>>(adjd, tt, n_t, k, b, par);                   \
+        }
+        EMPSO_TBA_CASE(1) EMPSO_TBA_CASE(2) EMPSO_TBA_CASE(3)
+#undef EMPSO_TBA_CASE
+    };
+
     // forward pass with u^n in ring slot (n mod 3); the checkpoint j holds
     // (u^{jK}, u^{jK-1}) for every jK <= nt - 2. The l2 misfit needs the pass
     // up to the last checkpoint only; the trace-normalised one needs whole
@@ -2365,7 +2674,9 @@ extern "C" int empso_gradient(const empso_problem *p, const float *vp_d, const f
         k_gab<<<ns, 256, 0, st>>>(runs, p->g.nrec);
     }
     // backward pass, segment by segment: segment j covers u^{jK-1} .. u^{e}
-    // in slots 0 .. e - jK + 1 (checkpoint 0 is the zero initial state)
+    // in slots 0 .. e - jK + 1 (checkpoint 0 is the zero initial state); the
+    // blocked adjoint carries its pair of psi levels across segments
+    int apar = 0;
     for (int j = last; j >= 0; --j) {
         const int b = j * K, e = std::min((j + 1) * K, nt - 1);
         if (j > 0) {
@@ -2376,12 +2687,21 @@ extern "C" int empso_gradient(const empso_problem *p, const float *vp_d, const f
             copy(sl.ck(0, 0), sl.seg(1));
         }
         for (int n = b; n < e; ++n) step_fwd(n, sl.seg(n - b + 1), sl.seg(n - b), sl.seg(n - b + 2), 0);
-        for (int k = e; k >= b + 1; --k)
-            step_adj(k, sl.adj(k + 1), sl.adj(k + 2), sl.adj(k), sl.seg(k - b + 1));
+        if (blocked) {
+            for (int k = e; k >= b + 1; apar ^= 1) {
+                const int T = (k - Ta + 1 >= b + 1) ? Ta : 1;
+                launch_adj(T, k, b, apar);
+                k -= T;
+            }
+        } else {
+            for (int k = e; k >= b + 1; --k)
+                step_adj(k, sl.adj(k + 1), sl.adj(k + 2), sl.adj(k), sl.seg(k - b + 1));
+        }
     }
     const int64_t npts = (int64_t)p->g.nz * p->g.nx;
     k_gfold<<<(int)std::min<int64_t>(2048, (npts + 255) / 256), 256, 0, st>>>(runs, ns, sh, sl.gacc(), vp_d, p->g.nz,
-                                                                              p->g.nx, p->g.nbl, p->g.dt, grad_d, illum_d);
+                                                                              p->g.nx, p->g.nbl, p->g.dt, blocked ? 1 : 0,
+                                                                              grad_d, illum_d);
     k_gmisfit<<<1, 256, 0, st>>>(runs, ns, p->g.nrec, norm ? 1 : 0, misfit_d);
     EMPSO_HIP(hipGetLastError());
     return EMPSO_OK;
