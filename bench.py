@@ -1,7 +1,7 @@
 """Benchmark of the fitness-evaluation hot path on one MI355X.
 
 Headline workload: the full search at scale, one EMPSO iteration of 128
-particles x 32 shots on the 601 x 1841 grid at 5 m (681 x 2001 with the
+particles x 32 shots on the 601 x 1841 grid at 5 m (681 x 1921 with the
 40-point absorbing layer), 921 receivers, 6 Hz Ricker, 4 s record (nt 21,636),
 8 x 20 control nodes: 4,096 forward runs, about 93 GB of wavefields resident
 in HBM. One iteration is 1.2e14 point-updates (over two minutes on the GPU),
@@ -100,13 +100,17 @@ def _counters_apply(d, per_launch_updates, tu, Nz):
 
 
 def committed_counter(name, key, per_launch_updates, tu, Nz):
-    """A per-launch figure from a committed counter summary (profiles/<name>),
-    if it was taken on the current kernel source with this tuning; else None."""
+    """A per-launch figure from a committed counter summary (profiles/<name>:
+    one measurement, or several under "entries", one per tiling), if one was
+    taken on the current kernel source with this tuning's tiles; else None."""
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
-    return d.get(key) if _counters_apply(d, per_launch_updates, tu, Nz) else None
+    for e in d.get("entries", [d]):
+        if _counters_apply(e, per_launch_updates, tu, Nz):
+            return e.get(key)
+    return None
 
 
 def damped_share(info):
@@ -166,8 +170,10 @@ def cpu_baseline(geom, dt, nt, steps, threads):
 def gradient_report(prob, dobs, reps=3):
     """Misfit gradient of a smooth starting model over the realistic
     geometry's 16 shots (outside the timed region): seconds per gradient with
-    HIP events, and the point-update rate of its three passes (forward with
-    checkpoints, segment recomputation, adjoint)."""
+    HIP events and the point-update rate of its passes, at the default
+    checkpoint interval (forward pass with checkpoints, segment recomputation,
+    adjoint: three passes) and, when the GPU has the memory, with every time
+    level kept (one forward pass and the adjoint)."""
     import torch
 
     from paper_1905_12795_amd import fd
@@ -175,19 +181,28 @@ def gradient_report(prob, dobs, reps=3):
     nz, nx = prob.info.nz, prob.info.nx
     z = np.arange(nz, dtype=np.float64)[:, None] / (nz - 1)
     v0 = torch.tensor(np.repeat(1500.0 + 4000.0 * z, nx, axis=1), dtype=torch.float32, device="cuda")
-    ws = fd.workspace(fd.lib.empso_gradient_workspace_bytes(prob.handle, 0))
-    fd.gradient(prob, v0, dobs, 0, ws)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        mis, _g = fd.gradient(prob, v0, dobs, 0, ws)
-    e1.record()
-    torch.cuda.synchronize()
-    sec = e0.elapsed_time(e1) / 1000.0 / reps
-    upd = 3 * prob.updates_per_run * prob.nshots
-    return {"workload": "realistic geometry, 16 shots, nt %d, a linear 1500-5500 m/s starting model" % prob.nt,
-            "seconds_per_gradient": sec, "gpt_updates_per_s_three_passes": upd / sec / 1e9,
-            "misfit": float(mis), "workspace_gib": ws.numel() / 2 ** 30}
+    out = {"workload": "realistic geometry, 16 shots, nt %d, a linear 1500-5500 m/s starting model" % prob.nt}
+    for name, K, passes in (("checkpointed", 0, 3), ("every_level_kept", prob.nt - 1, 2)):
+        need = fd.lib.empso_gradient_workspace_bytes(prob.handle, K)
+        if K and torch.cuda.mem_get_info()[0] < need + (8 << 30):
+            out[name] = {"skipped": "needs %.1f GB" % (need / 1e9)}
+            continue
+        ws = fd.workspace(need)
+        fd.gradient(prob, v0, dobs, K, ws)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            mis, _g = fd.gradient(prob, v0, dobs, K, ws)
+        e1.record()
+        torch.cuda.synchronize()
+        sec = e0.elapsed_time(e1) / 1000.0 / reps
+        upd = passes * prob.updates_per_run * prob.nshots
+        out[name] = {"checkpoint_every": K, "seconds_per_gradient": sec,
+                     "gpt_updates_per_s_over_passes": upd / sec / 1e9, "passes": passes,
+                     "misfit": float(mis), "workspace_gib": ws.numel() / 2 ** 30}
+        del ws
+        torch.cuda.empty_cache()
+    return out
 
 
 def _strict(v):
@@ -415,7 +430,7 @@ def main():
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1000.0 * wall / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "full: 601x1841 grid at 5 m + 40-point layer (681x2001), %d particles x 32 "
+        "config": {"workload": "full: 601x1841 grid at 5 m + 40-point layer (681x1921), %d particles x 32 "
                                "shots (%d runs, resident), 921 receivers, 6 Hz Ricker, 4 s (nt %d), 8x20 "
                                "nodes; one step = %d time steps of all runs of one EMPSO iteration's "
                                "evaluation (%d steps per iteration)"
@@ -423,7 +438,7 @@ def main():
                    "runs": npart * prob.nshots, "nt": prob.nt, "time_steps_per_step": block,
                    "time_steps_timed": tsteps_done, "iterations_completed": state["iterations"],
                    "tuning": tu.as_dict(), "autotuned": tuned},
-        "value_derivation": "fitness evals/s = point-updates/s / (32 shots x 681 x 2001 x %d updates per "
+        "value_derivation": "fitness evals/s = point-updates/s / (32 shots x 681 x 1921 x %d updates per "
                             "evaluation), from the timed steps' updates" % last,
         "gpt_updates_per_s": gpt,
         "gpt_updates_per_s_physical": phys_points * tsteps_done / wall / 1e9,

@@ -52,3 +52,26 @@ def test_counters_apply_only_to_the_same_kernel_and_tiles():
     assert not bench._counters_apply(_summary(), 999, _Tu(320, 4), 381)       # other batch
     assert not bench._counters_apply(_summary(kernel_source_sha256_16="0" * 16), 1000, _Tu(320, 4), 381)
 
+
+
+def test_committed_counter_picks_the_entry_of_the_launched_tiles(tmp_path, monkeypatch):
+    import json
+    e240 = _summary(tuning={"bz": 240, "tsteps": 4}, hbm=1.0)
+    e720 = _summary(tuning={"bz": 720, "tsteps": 4}, hbm=2.0)
+    (tmp_path / "profiles").mkdir()
+    (tmp_path / "profiles" / "x.json").write_text(json.dumps({"entries": [e240, e720]}))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: e240["kernel_source_sha256_16"])
+    assert bench.committed_counter("x.json", "hbm", 1000, _Tu(240, 4), 681) == 1.0
+    assert bench.committed_counter("x.json", "hbm", 1000, _Tu(720, 4), 681) == 2.0
+    assert bench.committed_counter("x.json", "hbm", 1000, _Tu(160, 4), 681) is None
+    assert bench.committed_counter("missing.json", "hbm", 1000, _Tu(240, 4), 681) is None
+
+
+def test_algorithmic_operations_weight_the_layer():
+    class _Info:
+        nz, nx, Nz, Nx = 601, 1841, 681, 1921
+    ops = bench.alg_ops_per_update(_Info)
+    share = 1 - 601 * 1841 / (681 * 2001)
+    assert abs(ops - (23 * (1 - share) + 29 * share)) < 1e-12 and 23.9 < ops < 24.0
+    assert abs(bench.VALU_PEAK_GOPS - 1024 * 16 * 2.4) < 1e-9
