@@ -322,10 +322,13 @@ int empso_default_tuning(empso_tuning *out);
  * 80, 160, 240, 320, 480, 720 and 1040 rows and temporal-blocking depth on
  * this batch (a
  * height that gives every grid the same strips as a lower one launches the
- * same tiles and is skipped) and write the fastest tuning to
- * *best (graph replay on) and its time per time step in microseconds to
- * *best_us_per_step (may be NULL). Every tuning gives bit-identical results.
- * Synchronises the stream; overwrites the workspace. */
+ * same tiles and is skipped), then time the three fastest again over about
+ * one second of launches each (after as many untimed ones: short bursts
+ * rank tilings that differ by a percent or two differently from a sustained
+ * run), and write the fastest of those to *best (graph replay on) and its
+ * time per time step in microseconds to *best_us_per_step (may be NULL).
+ * Takes a few seconds on large batches. Every tuning gives bit-identical
+ * results. Synchronises the stream; overwrites the workspace. */
 int empso_autotune_fitness(const empso_problem *const *probs, int32_t nprob, const float *const *obs_d,
                            const int32_t *prob_of_particle, int32_t np, const double *nodes_h, int32_t ld_nodes,
                            void *ws, size_t ws_bytes, empso_tuning *best, float *best_us_per_step,
