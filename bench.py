@@ -57,11 +57,14 @@ CYCLES_PER_VALU = 4
 VALU_PEAK_GOPS = SIMDS * LANES_PER_CYCLE * CLOCK_HZ / 1e9
 # Algorithmic VALU operations of one point-update as the scheme is evaluated
 # (one operation per add, multiply, fused multiply-add or reciprocal): the
-# Laplacian as a sum of small terms (20), the increment's difference, its FMA
-# with the coefficient, and the update (23); a damped point adds the damping
-# sum, 1 + a, its reciprocal, 1 - a, and two multiplies (29).
-OPS_UNDAMPED = 23
-OPS_DAMPED = 29
+# Laplacian as a sum of small terms (19: three adds per neighbour distance
+# for its z and x pairs, one FMA per distance with its weight, and one FMA per
+# distance but the farthest subtracting the centre), the increment's
+# difference, its FMA with the coefficient, and the update (22); a damped
+# point adds the damping sum, 1 + a, its reciprocal, 1 - a, and two
+# multiplies (28).
+OPS_UNDAMPED = 22
+OPS_DAMPED = 28
 
 
 def kernel_source_hash():

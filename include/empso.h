@@ -360,7 +360,11 @@ int empso_time_tuning(const empso_problem *const *probs, int32_t nprob, const fl
  * Checkpointing: (u^n, u^{n-1}) are kept every K = checkpoint_every steps
  * (0: K = ceil(sqrt(2 (nt - 1)))), and each segment is recomputed during the
  * backward pass: about two forward passes and one adjoint pass of work, and
- * K + 8 + 2 ceil((nt - 1)/K) fields per shot of memory. K >= nt - 1 keeps
+ * 2 (K + 2) + 6 + 2 ceil((nt - 1)/K) fields per shot of memory (two segment
+ * buffers: the next segment is recomputed on a second stream of the library's
+ * while the adjoint runs through the current one; the call's work still ends
+ * on the caller's stream). Both forward passes run the fitness kernel (the
+ * recomputation in a mode that keeps every time level). K >= nt - 1 keeps
  * every time level of one forward pass instead (one forward and one adjoint
  * pass; nt + 9 fields per shot, e.g. 234 GB for 16 shots of 381 x 1001 points
  * over 8114 steps). The adjoint advances up to three time steps per launch
@@ -379,7 +383,10 @@ size_t empso_gradient_workspace_bytes(const empso_problem *prob, int32_t checkpo
  * grad_d[nz][nx] (device FP32) = dJ/dvp, misfit_d[0] (device FP32) = J,
  * illum_d[nz][nx] (device FP32, may be NULL) = the source illumination.
  * ERANGE if a velocity lies outside [vmin, vmax]; EINVAL for NULL arguments,
- * nt < 2 or a negative interval; EWORKSPACE if ws_bytes is too small. */
+ * nt < 2 or a negative interval; EWORKSPACE if ws_bytes is too small; ENOTSUP
+ * for a grid whose stored field (padded grid plus a 16-point ring, rows
+ * rounded to 64 floats) takes 2^31 / 6 bytes or more. Calls on one device
+ * share the library's second stream there. */
 int empso_gradient(const empso_problem *prob, const float *vp_d, const float *obs_d, float *grad_d,
                    float *misfit_d, float *illum_d, int32_t checkpoint_every, void *ws, size_t ws_bytes,
                    empso_stream stream);

@@ -69,6 +69,14 @@ static const int kColsPerLane = 4;
 static const int kTileX = kLanesX * kColsPerLane;   // columns loaded by one wavefront
 static const int kQueue = 10;      // row-queue slots per level (9 stencil rows + 1 prefetch)
 static const int kMaxT = 4;        // deepest temporal blocking (4 kMaxT <= kRing)
+// The stencil's distance-3 and distance-4 weights are in the exact ratio
+// c4 / c3 = -9/128, so c3 (S3 - 4u) + c4 (S4 - 4u) = c3 (S3 - 4 (1 + c4/c3) u) + c4 S4
+// with the factor 4 (1 + c4/c3) = 119/32 exact in FP32 (per axis: half of it),
+// S_k the sum of the neighbours at distance k: one operation less per point,
+// and a constant field still gives an exactly zero Laplacian up to the
+// rounding of the coefficients themselves.
+static constexpr float kFold3 = 3.71875f;
+static constexpr float kFold3Axis = 1.859375f;
 
 }  // namespace empso
 
@@ -680,9 +688,17 @@ __device__ __forceinline__ float from_lane_above(float v) {
 // factors 1 - a_z and 1 / (1 + a_z) (tables built on the device with the
 // same reciprocal); otherwise in full. Each form is the full one with a
 // zero term, bit for bit, so the results do not depend on the tiling.
-template <int T, bool ISO>
+//
+// Record mode (REC, the misfit gradient's recomputation of a segment): the
+// run's fields are a segment's time levels, u^m in field m - b + 1 (b = the
+// segment's first step, fields R.fbytes apart from R.u[0]); the launch reads
+// u^n and u^{n-1} from fields n - b + 1 and n - b and stores every level's
+// owned rows, u^{n+l+1} into field n - b + 2 + l, so all T levels of the
+// launch are kept. No receivers are sampled (the descriptor's receiver row
+// is one no tile owns).
+template <int T, bool ISO, bool REC>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(T < 3 ? 3 : 2))) void k_tb(const RunDesc *__restrict__ runs, const int4 *__restrict__ tiles,
-                                            int ntiles, int n, int par) {
+                                            int ntiles, int n, int par, int b) {
     constexpr int NS = kQueue;
     constexpr int FILL = 8 * (T - 1);               // march steps before the first owned row
     constexpr int TQ = T > 1 ? T - 1 : 1;
@@ -702,9 +718,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(T < 3 ? 3 :
     // R.u[par]: a runtime index would move R to scratch memory). Reads that
     // run past a field land in the next field's zero ring or beyond the range
     // (zero); both only feed rows that are never stored.
-    const rsrc_t F = make_rsrc(R.u[0], 4u * R.fbytes);
+    const float *fbase = REC ? R.u[0] + (size_t)(n - b) * (R.fbytes >> 2) : R.u[0];
+    const rsrc_t F = make_rsrc(fbase, (REC ? (unsigned)(T + 2) : 4u) * R.fbytes);
     const int fb = (int)R.fbytes;
-    const int uin = par ? fb : 0, vin = par ? 3 * fb : 2 * fb;
+    const int uin = (REC || par) ? fb : 0, vin = REC ? 0 : (par ? 3 * fb : 2 * fb);
     const int uout = par ? 0 : fb, vout = par ? 2 * fb : 3 * fb;
     const rsrc_t Cf = make_rsrc(R.C, R.fbytes);
     const int c = t.z + 4 * lane;                   // stored column of this lane's first element
@@ -798,22 +815,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(T < 3 ? 3 :
                 const float u = v[4 + k2];
                 // Laplacian as a sum of small terms, farthest neighbours first:
                 // c_k ((u_{+k} + u_{-k}) - 2u) per axis, or with dz = dx
-                // c_k (((z pair) + (x pair)) - 4u). The centre weight is never
-                // formed, so no large partial sum cancels (FP32 accuracy over
-                // long runs).
+                // c_k (((z pair) + (x pair)) - 4u); the distance-4 pair's
+                // share of the centre is folded into the distance-3 term with
+                // an exact factor (kFold3). The centre weight is never formed,
+                // so no large partial sum cancels (FP32 accuracy over long
+                // runs).
                 float lap;
                 if (ISO) {
-                    lap = R.cz4 * fmaf(-4.0f, u, (pz4[k2] + mz4[k2]) + (v[0 + k2] + v[8 + k2]));
-                    lap = fmaf(R.cz3, fmaf(-4.0f, u, (pz3[k2] + mz3[k2]) + (v[1 + k2] + v[7 + k2])), lap);
+                    lap = R.cz4 * ((pz4[k2] + mz4[k2]) + (v[0 + k2] + v[8 + k2]));
+                    lap = fmaf(R.cz3, fmaf(-kFold3, u, (pz3[k2] + mz3[k2]) + (v[1 + k2] + v[7 + k2])), lap);
                     lap = fmaf(R.cz2, fmaf(-4.0f, u, (pz2[k2] + mz2[k2]) + (v[2 + k2] + v[6 + k2])), lap);
                     lap = fmaf(R.cz1, fmaf(-4.0f, u, (pz1[k2] + mz1[k2]) + (v[3 + k2] + v[5 + k2])), lap);
                 } else {
-                    lap = R.cz4 * fmaf(-2.0f, u, pz4[k2] + mz4[k2]);
-                    lap = fmaf(R.cz3, fmaf(-2.0f, u, pz3[k2] + mz3[k2]), lap);
+                    lap = R.cz4 * (pz4[k2] + mz4[k2]);
+                    lap = fmaf(R.cz3, fmaf(-kFold3Axis, u, pz3[k2] + mz3[k2]), lap);
                     lap = fmaf(R.cz2, fmaf(-2.0f, u, pz2[k2] + mz2[k2]), lap);
                     lap = fmaf(R.cz1, fmaf(-2.0f, u, pz1[k2] + mz1[k2]), lap);
-                    lap = fmaf(R.cx4, fmaf(-2.0f, u, v[0 + k2] + v[8 + k2]), lap);
-                    lap = fmaf(R.cx3, fmaf(-2.0f, u, v[1 + k2] + v[7 + k2]), lap);
+                    lap = fmaf(R.cx4, v[0 + k2] + v[8 + k2], lap);
+                    lap = fmaf(R.cx3, fmaf(-kFold3Axis, u, v[1 + k2] + v[7 + k2]), lap);
                     lap = fmaf(R.cx2, fmaf(-2.0f, u, v[2 + k2] + v[6 + k2]), lap);
                     lap = fmaf(R.cx1, fmaf(-2.0f, u, v[3 + k2] + v[5 + k2]), lap);
                 }
@@ -841,12 +860,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(T < 3 ? 3 :
             un = make_float4(uo[0], uo[1], uo[2], uo[3]);
             ue = ce;
             if (l < T - 1) qu[l][(k + 8) % NS] = un;
+            if constexpr (REC) {
+                const bool okl = own && (r >= s0) && (r < s1);
+                bst4(F, okl ? (2 + l) * fb + r * rowb + lcol : kDrop, un);
+            }
         }
-        const int rT = r1 - 4 * (T - 1);
-        const bool ok = own && (rT >= s0) && (rT < s1);
-        const int o = rT * rowb + lcol;
-        bst4(F, ok ? uout + o : kDrop, un);            // kDrop: dropped by the range check
-        bst4(F, ok ? vout + o : kDrop, ue);
+        if constexpr (!REC) {
+            const int rT = r1 - 4 * (T - 1);
+            const bool ok = own && (rT >= s0) && (rT < s1);
+            const int o = rT * rowb + lcol;
+            bst4(F, ok ? uout + o : kDrop, un);            // kDrop: dropped by the range check
+            bst4(F, ok ? vout + o : kDrop, ue);
+        }
     };
 
     auto step_any = [&](const int k, const int r1) __attribute__((always_inline)) {
@@ -1114,9 +1139,27 @@ static int launch_tb(int T, bool iso, const RunDesc *runs, const int4 *tiles, in
 #define EMPSO_TB_CASE(TT)                                                                 \
     if (T == TT) {                                                                        \
         if (iso)                                                                          \
-            k_tb<TT, true><<<blocks, 256, 0, st>>>(runs, tiles, ntiles, n, par);          \
+            k_tb<TT, true, false><<<blocks, 256, 0, st>>>(runs, tiles, ntiles, n, par, 0);   \
         else                                                                              \
-            k_tb<TT, false><<<blocks, 256, 0, st>>>(runs, tiles, ntiles, n, par);         \
+            k_tb<TT, false, false><<<blocks, 256, 0, st>>>(runs, tiles, ntiles, n, par, 0);  \
+        return EMPSO_OK;                                                                  \
+    }
+    EMPSO_TB_CASE(1) EMPSO_TB_CASE(2) EMPSO_TB_CASE(3) EMPSO_TB_CASE(4)
+#undef EMPSO_TB_CASE
+    return EMPSO_ENOTSUP;
+}
+
+// Record-mode launch (steps n .. n+T-1 of a segment that starts at step b).
+static int launch_tb_rec(int T, bool iso, const RunDesc *runs, const int4 *tiles, int ntiles, int n, int b,
+                         hipStream_t st) {
+    int blocks = (ntiles + 3) / 4;
+    blocks = (blocks + 7) / 8 * 8;
+#define EMPSO_TB_CASE(TT)                                                                 \
+    if (T == TT) {                                                                        \
+        if (iso)                                                                          \
+            k_tb<TT, true, true><<<blocks, 256, 0, st>>>(runs, tiles, ntiles, n, 0, b);      \
+        else                                                                              \
+            k_tb<TT, false, true><<<blocks, 256, 0, st>>>(runs, tiles, ntiles, n, 0, b);     \
         return EMPSO_OK;                                                                  \
     }
     EMPSO_TB_CASE(1) EMPSO_TB_CASE(2) EMPSO_TB_CASE(3) EMPSO_TB_CASE(4)
@@ -1486,6 +1529,23 @@ static __device__ __align__(256) double scratch[kScratchDoubles];
 static constexpr int kMaxDevices = 64;
 static std::mutex g_scratch_mu;
 static double *g_scratch_ptr[kMaxDevices];      // device address of scratch per device (NULL: not looked up)
+
+// A second stream per device for work that overlaps the caller's stream
+// (non-blocking, default priority), created on first use and kept until the
+// process ends. Calls that use it on one device share it, so their
+// overlapped parts run one after another; events order it against the
+// caller's stream.
+static std::mutex g_side_mu;
+static hipStream_t g_side[kMaxDevices];
+static int side_stream(hipStream_t *out) {
+    int dev = 0;
+    EMPSO_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) EMPSO_FAIL(EMPSO_ENOTSUP, "device %d beyond the library's table", dev);
+    std::lock_guard<std::mutex> lk(g_side_mu);
+    if (!g_side[dev]) EMPSO_HIP(hipStreamCreateWithFlags(&g_side[dev], hipStreamNonBlocking));
+    *out = g_side[dev];
+    return EMPSO_OK;
+}
 
 static int scratch_of_current_device(double **out) {
     int dev = 0;
@@ -1991,19 +2051,22 @@ struct GradShared {
     float cz1, cz2, cz3, cz4, cx1, cx2, cx3, cx4, wscale;
 };
 
-// Field slots of a run: 0 .. K+1 segment levels (the forward pass uses 0..2
-// as a ring), K+2 .. K+5 the adjoint's four contiguous fields (two pairs for
-// the blocked adjoint, a ring of three for the single-step one), K+6
-// gradient accumulator, K+7 illumination accumulator, then two per checkpoint.
+// Field slots of a run: nbuf buffers of K+2 segment levels each (with more
+// than one segment, two buffers: the next segment is recomputed into one
+// while the adjoint runs through the other), then the four contiguous fields
+// that hold the forward state during the checkpointing pass and the adjoint
+// afterwards (two pairs for the blocked adjoint, a ring of three for the
+// single-step one), the gradient accumulator, the illumination accumulator,
+// then two fields per checkpoint.
 struct GradSlots {
-    int K, ncheck;
-    int seg(int i) const { return i; }
-    int adjp() const { return K + 2; }
-    int adj(int k) const { return K + 2 + ((k % 3) + 3) % 3; }
-    int gacc() const { return K + 6; }
-    int illum() const { return K + 7; }
-    int ck(int j, int which) const { return K + 8 + 2 * j + which; }
-    int total() const { return K + 8 + 2 * ncheck; }
+    int K, ncheck, nbuf;
+    int seg(int buf, int i) const { return buf * (K + 2) + i; }
+    int adjp() const { return nbuf * (K + 2); }
+    int adj(int k) const { return adjp() + ((k % 3) + 3) % 3; }
+    int gacc() const { return adjp() + 4; }
+    int illum() const { return adjp() + 5; }
+    int ck(int j, int which) const { return adjp() + 6 + 2 * j + which; }
+    int total() const { return adjp() + 6 + 2 * ncheck; }
 };
 
 static int grad_interval(const empso_problem *p, int K) {
@@ -2011,26 +2074,29 @@ static int grad_interval(const empso_problem *p, int K) {
     return std::max(1, (int)std::ceil(std::sqrt(2.0 * std::max(1, p->g.nt - 1))));
 }
 
-// One time step of every run: out = cur + d with
-// d = [(1-a)(cur - prev) + C (Lap cur + s)] / (1+a). Forward (ADJ = false):
-// s = fsrc at the source point; with tsample set, the receivers add u^{k+1}^2
-// and u^{k+1} d^{k+1} to the trace sums. Adjoint (ADJ = true): s is the
+// One adjoint step of every run (the single-step adjoint, used when the
+// illumination is asked for): out = cur + d with
+// d = [(1-a)(cur - prev) + C (Lap cur + s)] / (1+a), where s is the
 // derivative of the misfit with respect to u^k at the receivers, u^k - d^k
 // (l2, accumulated into the misfit) or (a u^k - b d^k) / sd (trace-normalised),
 // and the gradient accumulator takes
 // u^k [(1+a)(psi^k - psi^{k+1}) - (1-a)(psi^{k+1} - psi^{k+2})]: the imaging
 // sum over k of psi^k times u's second time difference at k, rearranged by
 // parts (u^0 = u^{-1} = 0 and psi^{nt} = psi^{nt+1} = 0, so no boundary
-// terms), which needs one stored forward level per step instead of three.
+// terms), which needs one stored forward level per step instead of three;
+// the illumination accumulator takes (u^k)^2.
 // Thread (x, y) of block (bx, by, run) updates columns 4 (64 bx + x) .. +3 of
 // padded row kGRows by + y.
 static constexpr int kGRows = 4;     // rows per block of k_gstep
 static constexpr int kAdjT = 3;      // adjoint steps per launch of k_tba
 static constexpr int kAdjBz = 20;    // its tile height (16 shots fill the GPU only with short strips)
-template <bool ADJ, bool ISO>
+// tiling of the fitness-kernel passes when forward_shots has not tuned one
+// for the problem and shot count
+static constexpr int kGradFwdBz = 20;
+static constexpr int kGradFwdT = 2;
+template <bool ISO>
 __global__ __launch_bounds__(64 * kGRows) void k_gstep(const GradRun *__restrict__ runs, const GradShared sh, int cur,
-                                               int prev, int out, float fsrc, int k, int uk, int gacc, int illum,
-                                               int tsample) {
+                                               int prev, int out, int k, int uk, int gacc, int illum) {
     const int I = blockIdx.y * kGRows + (int)threadIdx.y;
     const int J0 = 4 * (blockIdx.x * 64 + (int)threadIdx.x);
     if (I >= sh.Nz || J0 >= sh.Nx) return;
@@ -2052,10 +2118,8 @@ __global__ __launch_bounds__(64 * kGRows) void k_gstep(const GradRun *__restrict
     const float pv[4] = {pv4.x, pv4.y, pv4.z, pv4.w}, Cv[4] = {C4.x, C4.y, C4.z, C4.w};
     const float cz[4] = {sh.cz1, sh.cz2, sh.cz3, sh.cz4}, cx[4] = {sh.cx1, sh.cx2, sh.cx3, sh.cx4};
     const float azr = sh.az[I];
-    float4 Uk4;
-    if (ADJ) Uk4 = ld4(R.fields + (size_t)uk * sh.gfs, o);
-    const float ukv[4] = {ADJ ? Uk4.x : 0.f, ADJ ? Uk4.y : 0.f, ADJ ? Uk4.z : 0.f, ADJ ? Uk4.w : 0.f};
-    float res[4];
+    const float4 Uk4 = ld4(R.fields + (size_t)uk * sh.gfs, o);
+    const float ukv[4] = {Uk4.x, Uk4.y, Uk4.z, Uk4.w};
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const float u = v[4 + q];
@@ -2064,58 +2128,45 @@ __global__ __launch_bounds__(64 * kGRows) void k_gstep(const GradRun *__restrict
         const float xs[4] = {v[q] + v[8 + q], v[1 + q] + v[7 + q], v[2 + q] + v[6 + q], v[3 + q] + v[5 + q]};
         float lap;
         if (ISO) {
-            lap = cz[3] * fmaf(-4.0f, u, zs[0] + xs[0]);
-            lap = fmaf(cz[2], fmaf(-4.0f, u, zs[1] + xs[1]), lap);
+            lap = cz[3] * (zs[0] + xs[0]);
+            lap = fmaf(cz[2], fmaf(-kFold3, u, zs[1] + xs[1]), lap);
             lap = fmaf(cz[1], fmaf(-4.0f, u, zs[2] + xs[2]), lap);
             lap = fmaf(cz[0], fmaf(-4.0f, u, zs[3] + xs[3]), lap);
         } else {
-            lap = cz[3] * fmaf(-2.0f, u, zs[0]);
-            lap = fmaf(cz[2], fmaf(-2.0f, u, zs[1]), lap);
+            lap = cz[3] * zs[0];
+            lap = fmaf(cz[2], fmaf(-kFold3Axis, u, zs[1]), lap);
             lap = fmaf(cz[1], fmaf(-2.0f, u, zs[2]), lap);
             lap = fmaf(cz[0], fmaf(-2.0f, u, zs[3]), lap);
-            lap = fmaf(cx[3], fmaf(-2.0f, u, xs[0]), lap);
-            lap = fmaf(cx[2], fmaf(-2.0f, u, xs[1]), lap);
+            lap = fmaf(cx[3], xs[0], lap);
+            lap = fmaf(cx[2], fmaf(-kFold3Axis, u, xs[1]), lap);
             lap = fmaf(cx[1], fmaf(-2.0f, u, xs[2]), lap);
             lap = fmaf(cx[0], fmaf(-2.0f, u, xs[3]), lap);
         }
         const int J = J0 + q;
-        res[q] = 0.0f;
-        if (!ADJ) {
-            if (s == R.srcS && c + q == R.srcC) lap += fsrc;
-        } else if (s == sh.recS && J < sh.Nx) {
+        if (s == sh.recS && J < sh.Nx) {
             const int r = sh.recmap[J];
             if (r >= 0) {
                 const float ob = R.obs[(size_t)k * sh.nrec + r];
+                float res;
                 if (R.ab) {
-                    res[q] = fmaf(R.ab[r], ukv[q], -R.ab[sh.nrec + r] * ob) * R.ab[2 * sh.nrec + r];
+                    res = fmaf(R.ab[r], ukv[q], -R.ab[sh.nrec + r] * ob) * R.ab[2 * sh.nrec + r];
                 } else {
-                    res[q] = ukv[q] - ob;
-                    R.acc[r] += (double)res[q] * (double)res[q];
+                    res = ukv[q] - ob;
+                    R.acc[r] += (double)res * (double)res;
                 }
-                lap += res[q];
+                lap += res;
             }
         }
-        (void)res;
         const float a = azr + ((J < sh.Nx) ? sh.ax[J] : 0.0f);
         const float d = fmaf(Cv[q], lap, (1.0f - a) * (u - pv[q])) * __builtin_amdgcn_rcpf(1.0f + a);
         const float un = u + d;
         R.fields[(size_t)out * sh.gfs + o + q] = un;
-        if (!ADJ && tsample && s == sh.recS && J < sh.Nx) {
-            const int r = sh.recmap[J];
-            if (r >= 0) {
-                const double dv = un, ov = R.obs[(size_t)(k + 1) * sh.nrec + r];
-                R.tsum[r] += dv * dv;
-                R.tsum[sh.nrec + r] += dv * ov;
-            }
-        }
-        if (ADJ) {
-            const float u0 = (&Uk4.x)[q];
-            float *g = R.fields + (size_t)gacc * sh.gfs + o + q;
-            *g = fmaf(u0, (1.0f + a) * (un - u) - (1.0f - a) * (u - pv[q]), *g);
-            if (illum) {
-                float *il = R.fields + (size_t)(gacc + 1) * sh.gfs + o + q;  // illumination: sum of u^k^2
-                *il = fmaf(u0, u0, *il);
-            }
+        const float u0 = ukv[q];
+        float *g = R.fields + (size_t)gacc * sh.gfs + o + q;
+        *g = fmaf(u0, (1.0f + a) * (un - u) - (1.0f - a) * (u - pv[q]), *g);
+        if (illum) {
+            float *il = R.fields + (size_t)(gacc + 1) * sh.gfs + o + q;  // illumination: sum of u^k^2
+            *il = fmaf(u0, u0, *il);
         }
     }
 }
@@ -2293,17 +2344,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                 const float u = v[4 + q];
                 float lap;
                 if (ISO) {
-                    lap = R.cz4 * fmaf(-4.0f, u, (pz4[q] + mz4[q]) + (v[0 + q] + v[8 + q]));
-                    lap = fmaf(R.cz3, fmaf(-4.0f, u, (pz3[q] + mz3[q]) + (v[1 + q] + v[7 + q])), lap);
+                    lap = R.cz4 * ((pz4[q] + mz4[q]) + (v[0 + q] + v[8 + q]));
+                    lap = fmaf(R.cz3, fmaf(-kFold3, u, (pz3[q] + mz3[q]) + (v[1 + q] + v[7 + q])), lap);
                     lap = fmaf(R.cz2, fmaf(-4.0f, u, (pz2[q] + mz2[q]) + (v[2 + q] + v[6 + q])), lap);
                     lap = fmaf(R.cz1, fmaf(-4.0f, u, (pz1[q] + mz1[q]) + (v[3 + q] + v[5 + q])), lap);
                 } else {
-                    lap = R.cz4 * fmaf(-2.0f, u, pz4[q] + mz4[q]);
-                    lap = fmaf(R.cz3, fmaf(-2.0f, u, pz3[q] + mz3[q]), lap);
+                    lap = R.cz4 * (pz4[q] + mz4[q]);
+                    lap = fmaf(R.cz3, fmaf(-kFold3Axis, u, pz3[q] + mz3[q]), lap);
                     lap = fmaf(R.cz2, fmaf(-2.0f, u, pz2[q] + mz2[q]), lap);
                     lap = fmaf(R.cz1, fmaf(-2.0f, u, pz1[q] + mz1[q]), lap);
-                    lap = fmaf(R.cx4, fmaf(-2.0f, u, v[0 + q] + v[8 + q]), lap);
-                    lap = fmaf(R.cx3, fmaf(-2.0f, u, v[1 + q] + v[7 + q]), lap);
+                    lap = fmaf(R.cx4, v[0 + q] + v[8 + q], lap);
+                    lap = fmaf(R.cx3, fmaf(-kFold3Axis, u, v[1 + q] + v[7 + q]), lap);
                     lap = fmaf(R.cx2, fmaf(-2.0f, u, v[2 + q] + v[6 + q]), lap);
                     lap = fmaf(R.cx1, fmaf(-2.0f, u, v[3 + q] + v[5 + q]), lap);
                 }
@@ -2398,20 +2449,6 @@ __global__ void k_gfold(const GradRun *__restrict__ runs, int nruns, const GradS
     }
 }
 
-// Trace-normalised misfit: sum over n of d^n_r^2 per run and receiver into
-// the third block of the trace sums (one block per run).
-__global__ __launch_bounds__(256) void k_gobs2(const GradRun *__restrict__ runs, int nrec, int nt) {
-    const GradRun R = runs[blockIdx.x];
-    for (int r = threadIdx.x; r < nrec; r += blockDim.x) {
-        double s = 0.0;
-        for (int n = 0; n < nt; ++n) {
-            const double o = R.obs[(size_t)n * nrec + r];
-            s += o * o;
-        }
-        R.tsum[2 * nrec + r] = s;
-    }
-}
-
 // Adjoint source of the trace-normalised misfit, the sum over traces of
 // m_r = 1/2 |d_r/sd_r - o_r/so_r|^2, sd_r = max(|d_r|, wd), so_r = max(|o_r|, wo),
 // wd = EMPSO_TRACE_FLOOR |d_k| (k the largest modelled trace, lowest index
@@ -2502,7 +2539,8 @@ __global__ __launch_bounds__(256) void k_gmisfit(const GradRun *__restrict__ run
 
 struct GradLayout {
     GradSlots sl;
-    size_t fb, runs_off, cd_off, adj_off, tiles_off, tiles1_off, acc_off, tsum_off, ab_off, C_off, fields_off, total;
+    size_t fb, runs_off, cd_off, adj_off, tiles_off, tiles1_off, fwd_runs_off, fwd_tiles_off, fwd_tiles1_off, acc_off,
+        tsum_off, ab_off, C_off, fields_off, total;
     int tile_cap;               // tile-table entries (all shots) for any tuning
 };
 
@@ -2510,16 +2548,21 @@ static GradLayout grad_layout(const empso_problem *p, int K) {
     GradLayout L;
     L.sl.K = grad_interval(p, K);
     L.sl.ncheck = (std::max(1, p->g.nt - 1) - 1) / L.sl.K + 1;     // checkpoints at 0, K, .. <= nt - 2
+    L.sl.nbuf = L.sl.ncheck > 1 ? 2 : 1;
     L.fb = field_bytes(p);
     size_t k = 0;
     auto take = [&](size_t b) { size_t r = k; k = align_up(k + b, 256); return r; };
     const int ns = p->g.nshots;
     L.runs_off = take(sizeof(GradRun) * ns);
     L.cd_off = take(sizeof(CoefDesc));
-    L.adj_off = take(sizeof(AdjDesc) * ns);
+    L.adj_off = take(sizeof(AdjDesc) * ns * L.sl.nbuf);          // one table per segment buffer
     L.tile_cap = tile_capacity(p) * ns;
     L.tiles_off = take(sizeof(int4) * (size_t)L.tile_cap);
     L.tiles1_off = take(sizeof(int4) * (size_t)L.tile_cap);
+    L.fwd_runs_off = take(sizeof(RunDesc) * ns * (1 + L.sl.nbuf));   // fitness-kernel passes: checkpointing,
+                                                                     // then record mode per segment buffer
+    L.fwd_tiles_off = take(sizeof(int4) * (size_t)L.tile_cap);
+    L.fwd_tiles1_off = take(sizeof(int4) * (size_t)L.tile_cap);
     L.acc_off = take(sizeof(double) * (size_t)ns * p->g.nrec);
     const bool norm = p->g.misfit == EMPSO_MISFIT_TRACE_NORMALISED;
     L.tsum_off = take(norm ? sizeof(double) * (3 * (size_t)p->g.nrec + 2) * ns : 0);
@@ -2546,6 +2589,11 @@ extern "C" int empso_gradient(const empso_problem *p, const float *vp_d, const f
     if (p->g.nt < 2) EMPSO_FAIL(EMPSO_EINVAL, "the gradient needs nt >= 2");
     if (reinterpret_cast<uintptr_t>(ws) % 256) EMPSO_FAIL(EMPSO_EINVAL, "workspace must be 256-byte aligned");
     const GradLayout L = grad_layout(p, checkpoint_every);
+    // record mode addresses kMaxT + 2 consecutive fields through one buffer
+    // resource with 32-bit byte offsets below 2^31 (kDrop must stay outside)
+    if ((uint64_t)(kMaxT + 2) * L.fb >= ((uint64_t)1 << 31))
+        EMPSO_FAIL(EMPSO_ENOTSUP, "grid too large for the gradient: a stored field takes %zu bytes (limit %llu)", L.fb,
+                   (unsigned long long)(((uint64_t)1 << 31) / (kMaxT + 2)));
     if (ws_bytes < L.total) EMPSO_FAIL(EMPSO_EWORKSPACE, "workspace %zu < %zu bytes", ws_bytes, L.total);
     hipStream_t st = (hipStream_t)stream;
     std::vector<float> vh((size_t)p->g.nz * p->g.nx);
@@ -2571,7 +2619,9 @@ extern "C" int empso_gradient(const empso_problem *p, const float *vp_d, const f
         hr[s].srcC = p->srcJ[s] + kRing;
     }
     GradRun *runs = reinterpret_cast<GradRun *>(w + L.runs_off);
-    EMPSO_HIP(hipMemcpy(runs, hr.data(), sizeof(GradRun) * ns, hipMemcpyHostToDevice));
+    // stream-ordered uploads (the caller's earlier work on st may still read
+    // the workspace), waited for before the host copies go
+    EMPSO_HIP(hipMemcpyAsync(runs, hr.data(), sizeof(GradRun) * ns, hipMemcpyHostToDevice, st));
     GradShared sh;
     sh.C = reinterpret_cast<const float *>(w + L.C_off);
     sh.az = p->d_az; sh.ax = p->d_ax; sh.wav = p->d_wav; sh.recmap = p->d_recmap;
@@ -2592,72 +2642,123 @@ extern "C" int empso_gradient(const empso_problem *p, const float *vp_d, const f
     cd.nz = p->g.nz; cd.nx = p->g.nx; cd.nbl = p->g.nbl; cd.Nz = p->Nz; cd.Nx = p->Nx; cd.S = p->S;
     cd.dt = (float)p->g.dt;
     CoefDesc *cdd = reinterpret_cast<CoefDesc *>(w + L.cd_off);
-    EMPSO_HIP(hipMemcpy(cdd, &cd, sizeof(CoefDesc), hipMemcpyHostToDevice));
+    EMPSO_HIP(hipMemcpyAsync(cdd, &cd, sizeof(CoefDesc), hipMemcpyHostToDevice, st));
+    EMPSO_HIP(hipStreamSynchronize(st));
     k_coef<<<dim3(1024, 1), 256, 0, st>>>(cdd);
 
     const dim3 blk(64, kGRows), grd((p->Nx + 255) / 256, (p->Nz + kGRows - 1) / kGRows, ns);
     const int cblocks = (int)std::min<size_t>(4096, (gfs / 4 + 255) / 256);
-    // the source value of step n is wavelet[n] / (dz dx), read on the host
-    std::vector<float> wav(nt);
-    EMPSO_HIP(hipMemcpy(wav.data(), p->d_wav, sizeof(float) * nt, hipMemcpyDeviceToHost));
-    auto step_fwd = [&](int n, int cur, int prev, int out, int tsample) {
-        const float fs = wav[n] * p->wscale;
-        if (iso)
-            k_gstep<false, true><<<grd, blk, 0, st>>>(runs, sh, cur, prev, out, fs, n, 0, 0, 0, tsample);
-        else
-            k_gstep<false, false><<<grd, blk, 0, st>>>(runs, sh, cur, prev, out, fs, n, 0, 0, 0, tsample);
-    };
     auto step_adj = [&](int k, int cur, int prev, int out, int uk) {
         if (iso)
-            k_gstep<true, true><<<grd, blk, 0, st>>>(runs, sh, cur, prev, out, 0.0f, k, uk, sl.gacc(),
-                                                     illum_d != nullptr, 0);
+            k_gstep<true><<<grd, blk, 0, st>>>(runs, sh, cur, prev, out, k, uk, sl.gacc(), illum_d != nullptr);
         else
-            k_gstep<true, false><<<grd, blk, 0, st>>>(runs, sh, cur, prev, out, 0.0f, k, uk, sl.gacc(),
-                                                      illum_d != nullptr, 0);
+            k_gstep<false><<<grd, blk, 0, st>>>(runs, sh, cur, prev, out, k, uk, sl.gacc(), illum_d != nullptr);
     };
-    auto copy = [&](int src, int dst) { k_gcopy<<<dim3(cblocks, ns), 256, 0, st>>>(runs, gfs, src, dst); };
+    auto copy = [&](hipStream_t s, int src, int dst) {
+        k_gcopy<<<dim3(cblocks, ns), 256, 0, s>>>(runs, gfs, src, dst);
+    };
 
-    // The blocked adjoint (k_tba, T adjoint steps per launch) unless the
+    // Tables of the checkpointing pass, which runs the fitness kernel on the
+    // four state fields (no receivers with the l2 misfit; the trace sums of
+    // the trace-normalised one), and of the blocked adjoint (k_tba, T adjoint
+    // steps per launch; one descriptor table per segment buffer), unless the
     // illumination is asked for, which the single-step adjoint accumulates.
     const bool blocked = illum_d == nullptr;
     const int Ta = kAdjT, bza = kAdjBz;
+    std::vector<const empso_problem *> pp(1, p);
+    std::vector<RunSpec> rsp;
+    for (int s = 0; s < ns; ++s) rsp.push_back(RunSpec{p, 0, s, nullptr, nullptr});
+    empso_tuning ftu;
+    {
+        std::lock_guard<std::mutex> lk(g_plan_mu);
+        const auto it = g_fwd_tuning.find(std::make_pair(p->uid, ns));
+        if (it != g_fwd_tuning.end()) {
+            ftu = it->second;                       // the tiling forward_shots chose for these shots
+        } else {
+            empso_default_tuning(&ftu);
+            ftu.bz = kGradFwdBz;
+            ftu.tsteps = kGradFwdT;
+        }
+    }
+    const RunDesc *fruns = reinterpret_cast<const RunDesc *>(w + L.fwd_runs_off);
+    const int4 *ftiles = reinterpret_cast<const int4 *>(w + L.fwd_tiles_off);
+    const int4 *ftiles1 = reinterpret_cast<const int4 *>(w + L.fwd_tiles1_off);
+    const int nft = tiles_of(p, ftu.bz, ftu.tsteps) * ns, nft1 = tiles_of(p, kTailBz, 1) * ns;
+    {
+        // table 0: the checkpointing pass on the state fields; table 1 + buf:
+        // record mode on segment buffer buf
+        std::vector<RunDesc> hf((size_t)ns * (1 + sl.nbuf));
+        for (int q = 0; q <= sl.nbuf; ++q)
+            for (int s = 0; s < ns; ++s) {
+                RunDesc &d = hf[(size_t)q * ns + s];
+                d = RunDesc{};
+                float *f = hr[s].fields + (size_t)(q == 0 ? sl.adjp() : sl.seg(q - 1, 0)) * gfs;
+                d.u[0] = f; d.u[1] = f + gfs; d.v[0] = f + 2 * gfs; d.v[1] = f + 3 * gfs;
+                d.C = sh.C;
+                const bool sums = norm && q == 0;
+                d.obs = sums ? hr[s].obs : nullptr;
+                d.traces = nullptr;
+                d.acc = sums ? hr[s].tsum : nullptr;    // [3][nrec] sums of d^2, d o, o^2
+                d.wav = p->d_wav; d.az = p->d_az; d.ax = p->d_ax; d.recmap = p->d_recmap; d.reccol = p->d_reccol;
+                d.zoma = p->d_zoma; d.zinv = p->d_zinv;
+                d.Nz = p->Nz; d.Nx = p->Nx; d.S = p->S; d.nrec = p->g.nrec;
+                d.recS = sums ? p->recI + kRing : -(1 << 30);   // otherwise no tile owns the receiver row
+                d.zlo = p->zlo; d.zhi = p->zhi;
+                d.norm = sums ? 1 : 0;
+                d.srcS = hr[s].srcS; d.srcC = hr[s].srcC;
+                d.nt = nt;
+                d.fbytes = (unsigned)L.fb;
+                d.c0 = p->c0;
+                d.cz1 = p->cz[0]; d.cz2 = p->cz[1]; d.cz3 = p->cz[2]; d.cz4 = p->cz[3];
+                d.cx1 = p->cx[0]; d.cx2 = p->cx[1]; d.cx3 = p->cx[2]; d.cx4 = p->cx[3];
+                d.wscale = p->wscale;
+            }
+        std::vector<int4> ht(L.tile_cap), ht1(L.tile_cap);
+        fill_tiles(ht.data(), pp, rsp, ftu.bz, ftu.tsteps);
+        fill_tiles(ht1.data(), pp, rsp, kTailBz, 1);
+        EMPSO_HIP(hipMemcpyAsync(w + L.fwd_runs_off, hf.data(), sizeof(RunDesc) * hf.size(), hipMemcpyHostToDevice,
+                                 st));
+        EMPSO_HIP(hipMemcpyAsync(w + L.fwd_tiles_off, ht.data(), sizeof(int4) * ht.size(), hipMemcpyHostToDevice, st));
+        EMPSO_HIP(hipMemcpyAsync(w + L.fwd_tiles1_off, ht1.data(), sizeof(int4) * ht1.size(), hipMemcpyHostToDevice,
+                                 st));
+        EMPSO_HIP(hipStreamSynchronize(st));        // the host tables may go once the copies are done
+    }
     AdjDesc *adjd = reinterpret_cast<AdjDesc *>(w + L.adj_off);
     int4 *tdA = reinterpret_cast<int4 *>(w + L.tiles_off), *tdA1 = reinterpret_cast<int4 *>(w + L.tiles1_off);
     int ntA = 0, ntA1 = 0;
     if (blocked) {
-        std::vector<AdjDesc> ha(ns);
-        for (int s = 0; s < ns; ++s) {
-            AdjDesc &a = ha[s];
-            a.psi = hr[s].fields + (size_t)sl.adjp() * gfs;
-            a.C = sh.C;
-            a.seg = hr[s].fields;
-            a.g = hr[s].fields + (size_t)sl.gacc() * gfs;
-            a.obs = hr[s].obs;
-            a.acc = hr[s].acc;
-            a.ab = hr[s].ab;
-            a.ax = p->d_ax; a.az = p->d_az; a.zoma = p->d_zoma; a.zinv = p->d_zinv;
-            a.recmap = p->d_recmap;
-            a.gfs = gfs;
-            a.Nz = p->Nz; a.Nx = p->Nx; a.S = p->S; a.nrec = p->g.nrec; a.recS = p->recI + kRing;
-            a.zlo = p->zlo; a.zhi = p->zhi;
-            a.fbytes = (unsigned)L.fb;
-            a.cz1 = p->cz[0]; a.cz2 = p->cz[1]; a.cz3 = p->cz[2]; a.cz4 = p->cz[3];
-            a.cx1 = p->cx[0]; a.cx2 = p->cx[1]; a.cx3 = p->cx[2]; a.cx4 = p->cx[3];
-        }
-        std::vector<const empso_problem *> pp(1, p);
-        std::vector<RunSpec> rsp;
-        for (int s = 0; s < ns; ++s) rsp.push_back(RunSpec{p, 0, s, nullptr, nullptr});
+        std::vector<AdjDesc> ha((size_t)ns * sl.nbuf);
+        for (int buf = 0; buf < sl.nbuf; ++buf)
+            for (int s = 0; s < ns; ++s) {
+                AdjDesc &a = ha[(size_t)buf * ns + s];
+                a.psi = hr[s].fields + (size_t)sl.adjp() * gfs;
+                a.C = sh.C;
+                a.seg = hr[s].fields + (size_t)sl.seg(buf, 0) * gfs;
+                a.g = hr[s].fields + (size_t)sl.gacc() * gfs;
+                a.obs = hr[s].obs;
+                a.acc = hr[s].acc;
+                a.ab = hr[s].ab;
+                a.ax = p->d_ax; a.az = p->d_az; a.zoma = p->d_zoma; a.zinv = p->d_zinv;
+                a.recmap = p->d_recmap;
+                a.gfs = gfs;
+                a.Nz = p->Nz; a.Nx = p->Nx; a.S = p->S; a.nrec = p->g.nrec; a.recS = p->recI + kRing;
+                a.zlo = p->zlo; a.zhi = p->zhi;
+                a.fbytes = (unsigned)L.fb;
+                a.cz1 = p->cz[0]; a.cz2 = p->cz[1]; a.cz3 = p->cz[2]; a.cz4 = p->cz[3];
+                a.cx1 = p->cx[0]; a.cx2 = p->cx[1]; a.cx3 = p->cx[2]; a.cx4 = p->cx[3];
+            }
         std::vector<int4> htA(L.tile_cap), htA1(L.tile_cap);
         fill_tiles(htA.data(), pp, rsp, bza, Ta);
         fill_tiles(htA1.data(), pp, rsp, kTailBz, 1);
         ntA = tiles_of(p, bza, Ta) * ns;
         ntA1 = tiles_of(p, kTailBz, 1) * ns;
-        EMPSO_HIP(hipMemcpyAsync(adjd, ha.data(), sizeof(AdjDesc) * ns, hipMemcpyHostToDevice, st));
+        EMPSO_HIP(hipMemcpyAsync(adjd, ha.data(), sizeof(AdjDesc) * ha.size(), hipMemcpyHostToDevice, st));
         EMPSO_HIP(hipMemcpyAsync(tdA, htA.data(), sizeof(int4) * htA.size(), hipMemcpyHostToDevice, st));
         EMPSO_HIP(hipMemcpyAsync(tdA1, htA1.data(), sizeof(int4) * htA1.size(), hipMemcpyHostToDevice, st));
-        EMPSO_HIP(hipStreamSynchronize(st));        // the host tables may go once the copies are done
+        EMPSO_HIP(hipStreamSynchronize(st));
     }
-    auto launch_adj = [&](int T, int k, int b, int par) {
+    auto launch_adj = [&](int T, int k, int b, int par, int buf) {
+        const AdjDesc *ad = adjd + (size_t)buf * ns;
         const int4 *tt = T == 1 ? tdA1 : tdA;
         const int n_t = T == 1 ? ntA1 : ntA;
         int blocks = (n_t + 3) / 4;
@@ -2665,58 +2766,120 @@ extern "C" int empso_gradient(const empso_problem *p, const float *vp_d, const f
 #define EMPSO_TBA_CASE(TT)                                                                           \
         if (T == TT) {                                                                                \
             if (iso)                                                                                  \
-                k_tba<TT, true><<<blocks, 256, 0, st>>>(adjd, tt, n_t, k, b, par);                    \
+                k_tba<TT, true><<<blocks, 256, 0, st>>>(ad, tt, n_t, k, b, par);                      \
             else                                                                                      \
-                k_tba<TT, false><<<blocks, 256, 0, st>>>(adjd, tt, n_t, k, b, par);                   \
+                k_tba<TT, false><<<blocks, 256, 0, st>>>(ad, tt, n_t, k, b, par);                     \
         }
         EMPSO_TBA_CASE(1) EMPSO_TBA_CASE(2) EMPSO_TBA_CASE(3)
 #undef EMPSO_TBA_CASE
     };
 
-    // forward pass with u^n in ring slot (n mod 3); the checkpoint j holds
-    // (u^{jK}, u^{jK-1}) for every jK <= nt - 2. The l2 misfit needs the pass
-    // up to the last checkpoint only; the trace-normalised one needs whole
-    // traces (their norms) before the adjoint starts, so it runs all steps,
-    // sampling the receivers, and then forms the adjoint-source weights.
+    // Checkpointing pass: the fitness kernel advances the state fields in
+    // launches of T steps (single steps where a checkpoint is not a multiple
+    // of T); after step jK the state pair holds (u^{jK}, u^{jK-1}), copied to
+    // checkpoint j, for every jK <= nt - 2. The l2 misfit needs the pass up
+    // to the last checkpoint only; the trace-normalised one needs whole
+    // traces (their norms) before the adjoint starts, so it runs all steps
+    // with the receivers sampled and then forms the adjoint-source weights.
     const int K = sl.K, last = sl.ncheck - 1;
-    auto ring = [](int n) { return ((n % 3) + 3) % 3; };
     const int nfwd = norm ? nt - 1 : last * K;
-    for (int n = 0; n < nfwd; ++n) {
-        step_fwd(n, ring(n), ring(n - 1), ring(n + 1), norm ? 1 : 0);
-        if ((n + 1) % K == 0 && (n + 1) / K <= last) {
-            const int j = (n + 1) / K;
-            copy(ring(n + 1), sl.ck(j, 0));
-            copy(ring(n), sl.ck(j, 1));
+    {
+        int n = 0, par = 0;
+        auto advance = [&](int n1) -> int {
+            while (n < n1) {
+                int rc;
+                if (n + ftu.tsteps <= n1) {
+                    rc = launch_tb(ftu.tsteps, iso, fruns, ftiles, nft, n, par, st);
+                    n += ftu.tsteps;
+                } else {
+                    rc = launch_tb(1, iso, fruns, ftiles1, nft1, n, par, st);
+                    n += 1;
+                }
+                if (rc) return rc;
+                par ^= 1;
+            }
+            return EMPSO_OK;
+        };
+        for (int j = 1; j <= last; ++j) {
+            const int rc = advance(j * K);
+            if (rc) EMPSO_FAIL(rc, "launch failed");
+            copy(st, sl.adjp() + par, sl.ck(j, 0));           // u^{jK} (field u of pair par)
+            copy(st, sl.adjp() + 2 + par, sl.ck(j, 1));       // u^{jK-1} (field v of pair par)
         }
+        const int rc = advance(nfwd);
+        if (rc) EMPSO_FAIL(rc, "launch failed");
+        if (norm) {
+            k_sample<<<dim3(8, ns), 256, 0, st>>>(fruns, ns, nt - 1, par);     // the last sample
+            k_gab<<<ns, 256, 0, st>>>(runs, p->g.nrec);
+        }
+        // the state fields become the adjoint's: psi^{nt} = psi^{nt+1} = 0
+        for (int s = 0; s < ns; ++s)
+            k_zero<<<256, 256, 0, st>>>(reinterpret_cast<float4 *>(hr[s].fields + (size_t)sl.adjp() * gfs),
+                                        (int64_t)(4 * gfs / 4));
     }
-    if (norm) {
-        k_gobs2<<<ns, 256, 0, st>>>(runs, p->g.nrec, nt);
-        k_gab<<<ns, 256, 0, st>>>(runs, p->g.nrec);
+
+    // Backward pass, segment by segment from the last: segment j covers
+    // u^{jK-1} .. u^{e}, restored from checkpoint j (checkpoint 0 is the zero
+    // initial state) and recomputed into slots 0 .. e - jK + 1 of buffer
+    // j mod 2; the blocked adjoint carries its pair of psi levels across
+    // segments. With two buffers, segment j - 1 is recomputed on a second
+    // stream while the adjoint runs through segment j on the caller's stream:
+    // each alone leaves most of the GPU idle with a few runs. Events order the
+    // buffers' reuse: a recomputation waits for the adjoint that last read its
+    // buffer, an adjoint for the recomputation of its segment.
+    hipStream_t st2 = st;
+    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};   // pass done, recomputed[2], adjoint done[2]
+    struct EventGuard {
+        hipEvent_t *e;
+        ~EventGuard() {
+            for (int k = 0; k < 5; ++k)
+                if (e[k]) (void)hipEventDestroy(e[k]);
+        }
+    } guard{ev};
+    if (sl.nbuf == 2) {
+        const int rc = side_stream(&st2);
+        if (rc) return rc;
+        for (int k = 0; k < 5; ++k) EMPSO_HIP(hipEventCreateWithFlags(&ev[k], hipEventDisableTiming));
+        EMPSO_HIP(hipEventRecord(ev[0], st));
+        EMPSO_HIP(hipStreamWaitEvent(st2, ev[0], 0));
     }
-    // backward pass, segment by segment: segment j covers u^{jK-1} .. u^{e}
-    // in slots 0 .. e - jK + 1 (checkpoint 0 is the zero initial state); the
-    // blocked adjoint carries its pair of psi levels across segments
-    int apar = 0;
-    for (int j = last; j >= 0; --j) {
+    // a segment's levels by the fitness kernel in record mode (launches of T
+    // steps, single steps for the rest)
+    auto recompute = [&](int j, int buf, hipStream_t s) -> int {
         const int b = j * K, e = std::min((j + 1) * K, nt - 1);
-        if (j > 0) {
-            copy(sl.ck(j, 1), sl.seg(0));
-            copy(sl.ck(j, 0), sl.seg(1));
-        } else {
-            copy(sl.ck(0, 1), sl.seg(0));                 // zero fields
-            copy(sl.ck(0, 0), sl.seg(1));
+        copy(s, sl.ck(j, 1), sl.seg(buf, 0));
+        copy(s, sl.ck(j, 0), sl.seg(buf, 1));
+        const RunDesc *rr = fruns + (size_t)(1 + buf) * ns;
+        for (int n = b; n < e;) {
+            const int T = n + ftu.tsteps <= e ? ftu.tsteps : 1;
+            const int rc = launch_tb_rec(T, iso, rr, T == 1 ? ftiles1 : ftiles, T == 1 ? nft1 : nft, n, b, s);
+            if (rc) return rc;
+            n += T;
         }
-        for (int n = b; n < e; ++n) step_fwd(n, sl.seg(n - b + 1), sl.seg(n - b), sl.seg(n - b + 2), 0);
+        return EMPSO_OK;
+    };
+    int apar = 0;
+    if (recompute(last, last % sl.nbuf, st)) EMPSO_FAIL(EMPSO_ENOTSUP, "launch failed");
+    for (int j = last; j >= 0; --j) {
+        const int b = j * K, e = std::min((j + 1) * K, nt - 1), buf = j % sl.nbuf;
+        if (j > 0) {                                         // then nbuf == 2
+            const int nb = (j - 1) % 2;
+            if (j + 1 <= last) EMPSO_HIP(hipStreamWaitEvent(st2, ev[3 + nb], 0));
+            if (recompute(j - 1, nb, st2)) EMPSO_FAIL(EMPSO_ENOTSUP, "launch failed");
+            EMPSO_HIP(hipEventRecord(ev[1 + nb], st2));
+        }
+        if (j < last) EMPSO_HIP(hipStreamWaitEvent(st, ev[1 + buf], 0));
         if (blocked) {
             for (int k = e; k >= b + 1; apar ^= 1) {
                 const int T = (k - Ta + 1 >= b + 1) ? Ta : 1;
-                launch_adj(T, k, b, apar);
+                launch_adj(T, k, b, apar, buf);
                 k -= T;
             }
         } else {
             for (int k = e; k >= b + 1; --k)
-                step_adj(k, sl.adj(k + 1), sl.adj(k + 2), sl.adj(k), sl.seg(k - b + 1));
+                step_adj(k, sl.adj(k + 1), sl.adj(k + 2), sl.adj(k), sl.seg(buf, k - b + 1));
         }
+        if (sl.nbuf == 2) EMPSO_HIP(hipEventRecord(ev[3 + buf], st));
     }
     const int64_t npts = (int64_t)p->g.nz * p->g.nx;
     k_gfold<<<(int)std::min<int64_t>(2048, (npts + 255) / 256), 256, 0, st>>>(runs, ns, sh, sl.gacc(), vp_d, p->g.nz,

@@ -214,3 +214,21 @@ def test_blocked_adjoint_equals_the_single_step_adjoint(gfd):
         _say(geom.__name__, "blocked vs single-step adjoint: gradient rel L2", e)
         assert torch.equal(m1, m2)
         assert e <= 1e-4
+
+
+def test_gradient_rejects_fields_beyond_its_32_bit_window(gfd):
+    """The segment recomputation addresses six consecutive stored fields with
+    32-bit byte offsets below 2^31: a grid whose stored field takes 2^31 / 6
+    bytes or more (here 10,032 x 10,048 floats, 403 MB, which the fitness
+    path still accepts) is refused with ENOTSUP before anything touches the
+    device buffers, which are therefore only placeholders."""
+    g = copy.deepcopy(config("tiny"))
+    g.update(nz=10000, nx=10000, nbl=0, tmax=0.01, ncz=2, ncx=3)
+    g["src"] = [[0.0, 500.0]]
+    g["rec"] = [[0.0, 10.0 * j] for j in range(0, 101)]
+    gp = gfd.Problem(g)
+    t = gfd.workspace(1024)
+    rc = gfd.lib.empso_gradient(gp.handle, gfd._ptr(t), gfd._ptr(t), gfd._ptr(t), gfd._ptr(t), None, 0,
+                                gfd._ptr(t), t.numel(), None)
+    assert rc == -6
+    assert b"too large for the gradient" in gfd.lib.empso_last_error()
