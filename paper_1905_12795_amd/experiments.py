@@ -130,6 +130,24 @@ def paired_ci(d, level=0.95):
     return m, m - h, m + h
 
 
+def load_pretrain_parts(paths):
+    """(X, f) of pretraining pairs saved in parts (`pretrain` outputs, or one
+    file): the parts are ordered by their first row and must tile the rows
+    [0, n) of one seeded draw without gaps or overlaps."""
+    parts = []
+    for q in paths:
+        d = np.load(q, allow_pickle=False)
+        start = int(d["start"]) if "start" in d.files else 0
+        parts.append((start, d["X"], d["f"]))
+    parts.sort(key=lambda t: t[0])
+    row = 0
+    for start, X, _f in parts:
+        if start != row:
+            raise ValueError("pretraining parts do not tile the rows: expected row %d, got %d" % (row, start))
+        row += len(X)
+    return np.concatenate([t[1] for t in parts]), np.concatenate([t[2] for t in parts])
+
+
 def surrogate_paired(workload, iters, seeds, N, K, M, pretrain_path, pretrain_n, pretrain_steps, log):
     """Plain EMPSO (N particles, all evaluated) against the surrogate screen
     (N particles x K candidate moves screened, the best-ranked M particles
@@ -143,19 +161,20 @@ def surrogate_paired(workload, iters, seeds, N, K, M, pretrain_path, pretrain_n,
     g["particles"] = N
     prob = fd.Problem(g)
     dobs = search.observed_for(g, prob, true_model(g))
-    if pretrain_path and os.path.exists(pretrain_path):
-        d = np.load(pretrain_path, allow_pickle=False)
-        X0, f0 = d["X"], d["f"]
-        _emit({"stage": "pretraining pairs loaded", "path": pretrain_path, "n": int(len(f0))})
+    parts = pretrain_path.split(",") if pretrain_path else []
+    if parts and all(os.path.exists(q) for q in parts):
+        X0, f0 = load_pretrain_parts(parts)
+        _emit({"stage": "pretraining pairs loaded", "paths": parts, "n": int(len(f0))})
     else:
         t0 = time.perf_counter()
         X0, f0 = search.pretrain_pairs(prob, dobs, g["node_lo"], g["node_hi"], pretrain_n, seed=1000)
         _emit({"stage": "pretraining pairs evaluated", "n": int(len(f0)), "seconds": time.perf_counter() - t0})
-        if pretrain_path:
-            np.savez(pretrain_path, X=X0, f=f0)
+        if len(parts) == 1:
+            np.savez(parts[0], X=X0, f=f0)
     rows = []
+    tunings = {}                 # one autotuned tiling per batch size (N plain, M screened)
     for seed in seeds:
-        hp = search.run(g, dobs, prob, iters, "plain", seed=seed, log_path=log)
+        hp = search.run(g, dobs, prob, iters, "plain", seed=seed, log_path=log, tunings=tunings)
         target = 1.01 * hp[-1]["best"]
         budget = hp[-1]["evaluations"]
         ep, tp = search.evals_to_reach(hp, target)
@@ -164,7 +183,7 @@ def surrogate_paired(workload, iters, seeds, N, K, M, pretrain_path, pretrain_n,
         for mode in ("screened", "random"):
             h = search.run(g, dobs, prob, 10 * iters, mode, seed=seed, K=K, evaluate=M, log_path=log,
                            pretrain=(X0, f0), pretrain_steps=pretrain_steps, target=target, max_evals=budget,
-                           gen=iters)
+                           gen=iters, tunings=tunings)
             e, t = search.evals_to_reach(h, target)
             row[mode + "_reached"] = bool(np.isfinite(e))
             row[mode + "_evals"] = e if np.isfinite(e) else h[-1]["evaluations"]
@@ -356,7 +375,8 @@ def main():
     sp.add_argument("--particles", type=int, default=128)
     sp.add_argument("--K", type=int, default=8)
     sp.add_argument("--evaluate", type=int, default=64)
-    sp.add_argument("--pretrain", default=None, help=".npz of (X, f) pairs: loaded if present, else written")
+    sp.add_argument("--pretrain", default=None, help=".npz of (X, f) pairs, or a comma-separated list of `pretrain` parts: "
+                         "loaded if present, else written")
     sp.add_argument("--pretrain-n", type=int, default=20000)
     sp.add_argument("--pretrain-steps", type=int, default=3000)
     sp.add_argument("--log", default=None)

@@ -87,7 +87,7 @@ def spearman(a, b):
 
 def run(geom, dobs, prob, iterations, mode="plain", seed=0, K=16, warmup=2, sur_kw=None, log_path=None,
         autotune=True, elitist=True, target=None, evaluate=None, pretrain=None, pretrain_steps=0, max_evals=None,
-        gen=None):
+        gen=None, tunings=None):
     """Run the search; returns the list of per-iteration records.
 
     Record fields: iteration, best, mean, median, evaluations (FD, cumulative),
@@ -106,6 +106,9 @@ def run(geom, dobs, prob, iterations, mode="plain", seed=0, K=16, warmup=2, sur_
     (X, f) are (particle, fitness) pairs from earlier FD runs that the
     surrogate holds and trains on (`pretrain_steps` Adam steps) before the
     search starts (untimed; the swarm then uses it from the first iteration).
+    `tunings` (a dict, batch size -> tuning) shares autotuned tilings between
+    runs: a batch size found there is not tuned again, a new one is tuned
+    and added.
     """
     N = geom["particles"]
     M = N if (mode == "plain" or evaluate is None) else int(evaluate)
@@ -128,8 +131,12 @@ def run(geom, dobs, prob, iterations, mode="plain", seed=0, K=16, warmup=2, sur_
                               evaluate=M, **kw)
     else:
         raise ValueError(mode)
-    if autotune:
+    if tunings is not None and M in tunings:
+        fb.tuning = tunings[M]
+    elif autotune:
         fb.autotune(swarm.ask())
+        if tunings is not None:
+            tunings[M] = fb.tuning
     out = []
     logf = open(log_path, "a") if log_path else None
     torch.cuda.synchronize()
