@@ -2089,11 +2089,15 @@ static int grad_interval(const empso_problem *p, int K) {
 // padded row kGRows by + y.
 static constexpr int kGRows = 4;     // rows per block of k_gstep
 static constexpr int kAdjT = 3;      // adjoint steps per launch of k_tba
-static constexpr int kAdjBz = 20;    // its tile height (16 shots fill the GPU only with short strips)
+static constexpr int kAdjBz = 40;    // its tile height (measured best with the overlapped recomputation)
 // tiling of the fitness-kernel passes when forward_shots has not tuned one
 // for the problem and shot count
 static constexpr int kGradFwdBz = 20;
 static constexpr int kGradFwdT = 2;
+// tile height and depth of the segment recomputation, which shares the GPU
+// with the adjoint (0: those of the checkpointing pass)
+static constexpr int kGradRecBz = 40;
+static constexpr int kGradRecT = 4;
 template <bool ISO>
 __global__ __launch_bounds__(64 * kGRows) void k_gstep(const GradRun *__restrict__ runs, const GradShared sh, int cur,
                                                int prev, int out, int k, int uk, int gacc, int illum) {
@@ -2539,7 +2543,8 @@ __global__ __launch_bounds__(256) void k_gmisfit(const GradRun *__restrict__ run
 
 struct GradLayout {
     GradSlots sl;
-    size_t fb, runs_off, cd_off, adj_off, tiles_off, tiles1_off, fwd_runs_off, fwd_tiles_off, fwd_tiles1_off, acc_off,
+    size_t fb, runs_off, cd_off, adj_off, tiles_off, tiles1_off, fwd_runs_off, fwd_tiles_off, fwd_tiles1_off, rec_tiles_off,
+        acc_off,
         tsum_off, ab_off, C_off, fields_off, total;
     int tile_cap;               // tile-table entries (all shots) for any tuning
 };
@@ -2563,6 +2568,7 @@ static GradLayout grad_layout(const empso_problem *p, int K) {
                                                                      // then record mode per segment buffer
     L.fwd_tiles_off = take(sizeof(int4) * (size_t)L.tile_cap);
     L.fwd_tiles1_off = take(sizeof(int4) * (size_t)L.tile_cap);
+    L.rec_tiles_off = take(sizeof(int4) * (size_t)L.tile_cap);
     L.acc_off = take(sizeof(double) * (size_t)ns * p->g.nrec);
     const bool norm = p->g.misfit == EMPSO_MISFIT_TRACE_NORMALISED;
     L.tsum_off = take(norm ? sizeof(double) * (3 * (size_t)p->g.nrec + 2) * ns : 0);
@@ -2684,6 +2690,9 @@ extern "C" int empso_gradient(const empso_problem *p, const float *vp_d, const f
     const int4 *ftiles = reinterpret_cast<const int4 *>(w + L.fwd_tiles_off);
     const int4 *ftiles1 = reinterpret_cast<const int4 *>(w + L.fwd_tiles1_off);
     const int nft = tiles_of(p, ftu.bz, ftu.tsteps) * ns, nft1 = tiles_of(p, kTailBz, 1) * ns;
+    const int rbz = kGradRecBz > 0 ? kGradRecBz : ftu.bz, rT = kGradRecT > 0 ? kGradRecT : ftu.tsteps;
+    const int4 *rtiles = reinterpret_cast<const int4 *>(w + L.rec_tiles_off);
+    const int nrt = tiles_of(p, rbz, rT) * ns;
     {
         // table 0: the checkpointing pass on the state fields; table 1 + buf:
         // record mode on segment buffer buf
@@ -2720,6 +2729,10 @@ extern "C" int empso_gradient(const empso_problem *p, const float *vp_d, const f
                                  st));
         EMPSO_HIP(hipMemcpyAsync(w + L.fwd_tiles_off, ht.data(), sizeof(int4) * ht.size(), hipMemcpyHostToDevice, st));
         EMPSO_HIP(hipMemcpyAsync(w + L.fwd_tiles1_off, ht1.data(), sizeof(int4) * ht1.size(), hipMemcpyHostToDevice,
+                                 st));
+        std::vector<int4> htr(L.tile_cap);
+        fill_tiles(htr.data(), pp, rsp, rbz, rT);
+        EMPSO_HIP(hipMemcpyAsync(w + L.rec_tiles_off, htr.data(), sizeof(int4) * htr.size(), hipMemcpyHostToDevice,
                                  st));
         EMPSO_HIP(hipStreamSynchronize(st));        // the host tables may go once the copies are done
     }
@@ -2851,8 +2864,8 @@ extern "C" int empso_gradient(const empso_problem *p, const float *vp_d, const f
         copy(s, sl.ck(j, 0), sl.seg(buf, 1));
         const RunDesc *rr = fruns + (size_t)(1 + buf) * ns;
         for (int n = b; n < e;) {
-            const int T = n + ftu.tsteps <= e ? ftu.tsteps : 1;
-            const int rc = launch_tb_rec(T, iso, rr, T == 1 ? ftiles1 : ftiles, T == 1 ? nft1 : nft, n, b, s);
+            const int T = n + rT <= e ? rT : 1;
+            const int rc = launch_tb_rec(T, iso, rr, T == 1 ? ftiles1 : rtiles, T == 1 ? nft1 : nrt, n, b, s);
             if (rc) return rc;
             n += T;
         }
