@@ -10,6 +10,10 @@
       plain EMPSO (128 particles) against the surrogate screen (1024
       candidates, the best-ranked 64 evaluated, a network pretrained on 20k
       FD pairs) and a random screen, on 12 paired seeds, with 95 % intervals.
+  python -m paper_1905_12795_amd.experiments surrogate-ranking --workload mini
+      the network's choice of one move among K candidates against a random
+      choice among the same candidates (all evaluated by the FD fitness), on
+      16 seeds at three states of the swarm, with 95 % intervals.
   python -m paper_1905_12795_amd.experiments surrogate --workload realistic --iters 15 --seeds 1
       plain vs surrogate-screened vs randomly screened EMPSO on the same
       seeds; FD evaluations and wall time until each reaches 1.01 x the plain
@@ -207,6 +211,70 @@ def surrogate_paired(workload, iters, seeds, N, K, M, pretrain_path, pretrain_n,
     _emit(summ)
 
 
+def surrogate_ranking(workload, seeds, states, K, emit=True):
+    """What the trained network adds where it acts: the choice of one move
+    among K candidates. Per seed, plain EMPSO runs while a network trains
+    online on every evaluated (position, misfit) pair (the screened search's
+    schedule: 64 Adam steps per iteration); after each iteration count in
+    `states`, every particle draws K candidate moves from the swarm's state,
+    the FD fitness evaluates all K N of them, and the network's choice (lowest
+    prediction) is compared with a uniformly random choice among the same
+    candidates, whose expected log-misfit is the candidates' mean: a uniformly
+    random choice among K independent draws is the move of plain EMPSO. Per
+    seed, averaged over the states: the Spearman correlation of prediction and
+    FD misfit over all candidates (0 for a random ranking), the mean over
+    particles of E[log f(random choice)] - log f(network's choice) (positive:
+    the network's moves are better) next to the same gain of the best
+    candidate (the most any ranking can gain), and the fraction of particles
+    whose network choice beats the candidates' median. Summary: means over
+    seeds with 95 % t intervals. Returns (rows, summary)."""
+    from .pso import EMPSO
+    from .surrogate import Surrogate, candidate_moves
+    g = config(workload)
+    prob = fd.Problem(g)
+    dobs = search.observed_for(g, prob, true_model(g))
+    N, lo, hi = g["particles"], g["node_lo"], g["node_hi"]
+    fb = fd.FitnessBatch([prob], [dobs], [0] * N)
+    fb.autotune(uniform_particles(N, lo, hi, 0))
+    states = sorted(int(k) for k in states)
+    rows = []
+    for seed in seeds:
+        swarm = EMPSO(lo, hi, N, gen=max(states[-1], 10), seed=seed)
+        sur = Surrogate(lo, hi, seed=seed)
+        rng = np.random.Generator(np.random.PCG64(seed + 5000))
+        per = []
+        for it in range(1, states[-1] + 1):
+            x = swarm.ask()
+            f = fb(x).cpu().numpy().astype(np.float64)
+            sur.add(x, f)
+            sur.train()
+            swarm.tell(f)
+            if it not in states:
+                continue
+            cand = candidate_moves(swarm, K, rng)
+            fc = np.stack([fb(cand[k]).cpu().numpy().astype(np.float64) for k in range(K)])     # [K][N]
+            pred = sur.predict(cand.reshape(-1, swarm.D)).reshape(K, N)
+            lf = np.log(fc)
+            chosen = lf[np.argmin(pred, axis=0), np.arange(N)]
+            per.append({"rho": search.spearman(pred.ravel(), fc.ravel()),
+                        "log_gain": float(np.mean(lf.mean(axis=0) - chosen)),
+                        "best_log_gain": float(np.mean(lf.mean(axis=0) - lf.min(axis=0))),
+                        "beats_median": float(np.mean(chosen < np.median(lf, axis=0)))})
+        row = {"seed": seed, "states": states, "K": K, "particles": N}
+        for key in per[0]:
+            row[key] = float(np.mean([q[key] for q in per]))
+        rows.append(row)
+        if emit:
+            _emit(dict(row, workload=workload))
+    summ = {"workload": workload, "seeds": list(seeds), "states": states, "K": K}
+    for key in ("rho", "log_gain", "best_log_gain", "beats_median"):
+        m, lo95, hi95 = paired_ci([r[key] for r in rows])
+        summ[key] = {"mean": m, "ci95": [lo95, hi95]}
+    if emit:
+        _emit(summ)
+    return rows, summ
+
+
 def pretrain(workload, total, start, stop, out):
     """Rows [start, stop) of the seeded uniform draw of `total` particles,
     evaluated by the FD fitness, saved as (X, f) to `out` (.npz)."""
@@ -380,6 +448,11 @@ def main():
     sp.add_argument("--pretrain-n", type=int, default=20000)
     sp.add_argument("--pretrain-steps", type=int, default=3000)
     sp.add_argument("--log", default=None)
+    rk = sub.add_parser("surrogate-ranking")
+    rk.add_argument("--workload", default="mini", choices=["mini", "realistic"])
+    rk.add_argument("--seeds", default="1,2,3,4,5,6,7,8,9,10,11,12,13,14,15,16")
+    rk.add_argument("--states", default="6,12,18", help="iteration counts after which the candidates are ranked")
+    rk.add_argument("--K", type=int, default=16)
     pt = sub.add_parser("pretrain")
     pt.add_argument("--workload", default="realistic", choices=["mini", "realistic"])
     pt.add_argument("--total", type=int, default=20000)
@@ -414,6 +487,9 @@ def main():
         mlp_timing(a.reps)
     elif a.cmd == "bandwidth":
         bandwidth(a.mib, a.reps)
+    elif a.cmd == "surrogate-ranking":
+        surrogate_ranking(a.workload, [int(x) for x in a.seeds.split(",")], [int(x) for x in a.states.split(",")],
+                          a.K)
     elif a.cmd == "pretrain":
         pretrain(a.workload, a.total, a.start, a.stop if a.stop is not None else a.total, a.out)
     elif a.cmd == "surrogate-paired":

@@ -352,6 +352,23 @@ class ScreenedEMPSO(EMPSO):
         return self.history[-1]
 
 
+def candidate_moves(swarm, K, rng):
+    """K independent draws of the Eq. 1-2 move of every particle from the
+    swarm's current state (positions, velocities, personal and global bests),
+    with the velocity clamp and the box clamp: [K][N][D] positions. The
+    random vectors come from `rng`, so the swarm's own generator is not
+    touched; the arithmetic is that of ScreenedEMPSO's candidates."""
+    g = swarm.g
+    out = np.empty((int(K), swarm.N, swarm.D))
+    for k in range(int(K)):
+        u1 = rng.random((swarm.N, swarm.D))
+        u2 = rng.random((swarm.N, swarm.D))
+        v = swarm.chi * (swarm.v + swarm.c1 * u1 * (swarm.p - swarm.x) + swarm.c2 * u2 * (g - swarm.x))
+        v = np.minimum(np.maximum(v, -swarm.vclamp), swarm.vclamp)
+        out[k] = np.minimum(np.maximum(swarm.x + v, swarm.lo), swarm.hi)
+    return out
+
+
 def save_surrogate(path, sur):
     """A surrogate's state (Surrogate.state_dict) in one .npz: arrays as arrays,
     the rest as JSON text; no pickles."""

@@ -1,35 +1,40 @@
-"""What the trained surrogate gains over the search without it (run on an MI355X).
+"""What the trained surrogate gains over the method without it (run on an MI355X).
 
-Plain EMPSO and surrogate-screened EMPSO (K = 16 candidate moves per particle,
-the network ranks them, each particle's best-ranked move goes to the
-finite-difference fitness) run on the same GPU, problem and seeds; a random
-ranking of the same candidates is the ablation. A single search is chaotic (a
-change in the last bit of one fitness value changes the whole trajectory), so
-the claims are made on the seed average of the best-misfit-so-far curves
-(eight seeds, equal FD evaluations per iteration in every mode):
+The network acts at one place in the screened search: each particle draws K
+candidate moves (independent draws of Eq. 1's random vectors) and the network
+picks one. A uniformly random pick among K independent draws has the
+distribution of plain EMPSO's single draw, so the network's pick against a
+random pick among the same candidates is exactly the network's contribution,
+measured without the chaos of whole searches (a last-bit change in one fitness
+value changes a whole trajectory, which makes seed-averaged search curves
+noisy; the search-level comparison is a study, not a test).
 
-* the screened curve reaches 1.01 x the plain curve's final value with fewer
-  FD evaluations and in less wall time (network training and inference
-  included) than the plain search spends in all;
-* over the second two thirds of the search the screened curve lies below the
-  randomly screened one on average (the network ranks better than chance).
-
-The GPU fitness and the network are deterministic, so the curves are
-reproducible for a given build. Parity of these gains against the paper is
-unpinned (the surrogate is not in the paper).
+Mini problem (101 x 301 at 10 m, 4 shots, 3 x 6 nodes, 32 particles), 16
+seeds: plain EMPSO runs while the network trains online on every evaluated
+pair (64 Adam steps per iteration); after iterations 6, 12 and 18 every
+particle draws K = 16 candidates and the FD fitness evaluates all of them.
+Per seed (averaged over the three states): the Spearman correlation between
+the network's prediction and the FD misfit over all 512 candidates, which is
+0 in expectation for a random ranking, and the log-misfit gain of the
+network's pick over a random pick (the candidates' mean log-misfit minus the
+pick's). The test asserts that the 95 % t intervals of both means over the
+16 seeds lie above zero (the ranking is better than chance and the moves it
+picks are better than plain EMPSO's, with the seed-to-seed spread as the
+noise calibration), and that the gain stays below the best candidate's (the
+most any ranking can gain). The GPU fitness and the network are
+deterministic, so the figures are reproducible for a given build. Parity of
+these gains against the paper is unpinned (the surrogate is not in the
+paper).
 """
 import sys
 
-import numpy as np
 import pytest
 import torch
 
-from workloads.configs import config, true_model
-
 pytestmark = pytest.mark.gpu
 
-SEEDS = tuple(range(1, 9))
-ITERS = 30
+SEEDS = tuple(range(1, 17))
+STATES = (6, 12, 18)
 
 
 def _say(*a):
@@ -37,27 +42,16 @@ def _say(*a):
 
 
 @pytest.mark.timeout(900)
-def test_screened_search_reaches_plain_misfit_with_fewer_evaluations():
+def test_network_ranks_candidate_moves_better_than_chance():
     assert torch.cuda.is_available(), "GPU tests need an MI355X"
-    from paper_1905_12795_amd import fd, search
-    g = config("mini")
-    prob = fd.Problem(g)
-    dobs = search.observed_data(prob, true_model(g))
-    runs = {m: [] for m in ("plain", "screened", "random")}
-    for seed in SEEDS:
-        for m in runs:
-            runs[m].append(search.run(g, dobs, prob, ITERS, m, seed=seed, K=16))
-        _say("seed", seed, {m: round(runs[m][-1][-1]["best"], 3) for m in runs})
-    mean = {m: search.mean_history(h) for m, h in runs.items()}
-    plain = mean["plain"][-1]
-    target = 1.01 * plain["best"]
-    e, t = search.evals_to_reach(mean["screened"], target)
-    _say("plain mean final", plain["best"], plain["evaluations"], "%.3fs" % plain["wall_s"],
-         "screened reaches 1.01x at", e, "evals", "%.3fs" % t)
-    assert e < plain["evaluations"]
-    assert t < plain["wall_s"]
-    b = {m: np.array([r["best"] for r in mean[m]]) for m in mean}
-    k0 = ITERS // 3
-    gap = float(np.mean(b["screened"][k0:] - b["random"][k0:]))
-    _say("mean gap screened - random over iterations %d..%d: %.4f" % (k0 + 1, ITERS, gap))
-    assert gap < 0
+    from paper_1905_12795_amd import experiments
+    rows, summ = experiments.surrogate_ranking("mini", SEEDS, STATES, 16, emit=False)
+    for r in rows:
+        _say("seed", r["seed"], "rho %.3f" % r["rho"], "log gain %.4f" % r["log_gain"],
+             "best-candidate gain %.4f" % r["best_log_gain"], "beats median %.3f" % r["beats_median"])
+    _say("summary", summ)
+    assert len(rows) == len(SEEDS)
+    assert summ["rho"]["ci95"][0] > 0.0, summ["rho"]
+    assert summ["log_gain"]["ci95"][0] > 0.0, summ["log_gain"]
+    # the network's pick can gain at most what the best candidate gains
+    assert summ["log_gain"]["mean"] <= summ["best_log_gain"]["mean"]

@@ -105,3 +105,30 @@ def test_screened_swarm_checkpoint_resumes_bitwise(tmp_path):
         ra, rb = a.tell(f(a.ask())), b.tell(f(b.ask()))
         assert ra == rb
     assert np.array_equal(a.x, b.x) and np.array_equal(a.sel, b.sel) and np.array_equal(a.p, b.p)
+
+
+def test_candidate_moves_draw_the_empso_move():
+    """candidate_moves (the ranking study's candidates) draws Eq. 1-2 moves
+    with the swarm's arithmetic: from the state tell() reaches after the
+    bests update, one candidate drawn from a copy of the swarm's generator is
+    the swarm's own move (mutation off); every candidate lies in the box."""
+    import copy
+
+    from paper_1905_12795_amd.surrogate import candidate_moves
+    lo, hi, c = _box(D=7, seed=4)
+    a = pso.EMPSO(lo, hi, 12, gen=8, seed=5, elitist=False)
+    for _ in range(3):
+        a.tell(np.sum((a.ask() - c) ** 2, axis=1))
+    f = np.sum((a.ask() - c) ** 2, axis=1)
+    b = copy.deepcopy(a)
+    a.tell(f)
+    better = f < b.fp
+    b.fp = np.where(better, f, b.fp)
+    b.p = np.where(better[:, None], b.x, b.p)
+    b.gi = int(np.argmin(b.fp))
+    one = candidate_moves(b, 1, copy.deepcopy(b.rng))
+    assert np.array_equal(one[0], a.x)
+    many = candidate_moves(b, 5, np.random.Generator(np.random.PCG64(9)))
+    assert many.shape == (5, 12, 7)
+    assert np.all(many >= lo) and np.all(many <= hi)
+    assert not np.array_equal(many[0], many[1])
