@@ -219,13 +219,16 @@ def _strict(v):
     return v
 
 
-def surrogate_report(seeds=(1, 2, 3, 4), iters=30):
+def surrogate_report(seeds=(1, 2, 3, 4), iters=30, rank_seeds=tuple(range(1, 9))):
     """Surrogate vs plain (outside the timed region): the seed average of the
-    mini search's best-misfit curves, plus the network's inference on 1024
+    mini search's best-misfit curves; the network's choice among 16 candidate
+    moves against a random choice among the same candidates (all evaluated by
+    the FD fitness, after 6, 12 and 18 iterations of online training, with
+    95 % intervals over the seeds); and the network's inference on 1024
     candidates and one training step (batch 256) timed with HIP events."""
     import torch
 
-    from paper_1905_12795_amd import fd, search
+    from paper_1905_12795_amd import experiments, fd, search
     from paper_1905_12795_amd.surrogate import Surrogate
     from workloads.configs import config, true_model
     from workloads.models import uniform_particles
@@ -242,6 +245,10 @@ def surrogate_report(seeds=(1, 2, 3, 4), iters=30):
            "plain_final_misfit": hp[-1]["best"], "plain_fd_evals": hp[-1]["evaluations"],
            "plain_wall_s": hp[-1]["wall_s"], "screened_final_misfit": hs[-1]["best"],
            "screened_fd_evals_to_plain_final": finite(e), "screened_wall_s_to_plain_final": finite(t)}
+    _rows, rk = experiments.surrogate_ranking("mini", rank_seeds, (6, 12, 18), 16, emit=False)
+    rep["candidate_ranking"] = dict(rk, note="per seed: Spearman of prediction and FD misfit over all 512 "
+                                             "candidates; log-misfit gain of the network's pick over a random "
+                                             "pick among the same candidates, and of the best candidate")
     # network timings at the surrogate workload's shape (D = 60, H = 256)
     gs = config("surrogate")
     sur = Surrogate(gs["node_lo"], gs["node_hi"], seed=0)
