@@ -2090,8 +2090,9 @@ static int grad_interval(const empso_problem *p, int K) {
 static constexpr int kGRows = 4;     // rows per block of k_gstep
 static constexpr int kAdjT = 3;      // adjoint steps per launch of k_tba
 static constexpr int kAdjBz = 40;    // its tile height (measured best with the overlapped recomputation)
-// tiling of the fitness-kernel passes when forward_shots has not tuned one
-// for the problem and shot count
+// tile height and depth of the checkpointing pass (measured on 16 realistic
+// shots: 0.489 s per gradient, against 0.526 s at the tiling the forward
+// modelling's autotuner picks for the same shots, one step per launch)
 static constexpr int kGradFwdBz = 20;
 static constexpr int kGradFwdT = 2;
 // tile height and depth of the segment recomputation, which shares the GPU
@@ -2675,17 +2676,9 @@ extern "C" int empso_gradient(const empso_problem *p, const float *vp_d, const f
     std::vector<RunSpec> rsp;
     for (int s = 0; s < ns; ++s) rsp.push_back(RunSpec{p, 0, s, nullptr, nullptr});
     empso_tuning ftu;
-    {
-        std::lock_guard<std::mutex> lk(g_plan_mu);
-        const auto it = g_fwd_tuning.find(std::make_pair(p->uid, ns));
-        if (it != g_fwd_tuning.end()) {
-            ftu = it->second;                       // the tiling forward_shots chose for these shots
-        } else {
-            empso_default_tuning(&ftu);
-            ftu.bz = kGradFwdBz;
-            ftu.tsteps = kGradFwdT;
-        }
-    }
+    empso_default_tuning(&ftu);
+    ftu.bz = kGradFwdBz;
+    ftu.tsteps = kGradFwdT;
     const RunDesc *fruns = reinterpret_cast<const RunDesc *>(w + L.fwd_runs_off);
     const int4 *ftiles = reinterpret_cast<const int4 *>(w + L.fwd_tiles_off);
     const int4 *ftiles1 = reinterpret_cast<const int4 *>(w + L.fwd_tiles1_off);
