@@ -2044,7 +2044,7 @@ struct GradRun {
 };
 
 struct GradShared {
-    const float *C, *az, *ax, *wav;
+    const float *C, *az, *ax;
     const int *recmap;
     size_t gfs;                 // floats per field
     int Nz, Nx, S, nrec, recS, nt;
@@ -2544,9 +2544,8 @@ __global__ __launch_bounds__(256) void k_gmisfit(const GradRun *__restrict__ run
 
 struct GradLayout {
     GradSlots sl;
-    size_t fb, runs_off, cd_off, adj_off, tiles_off, tiles1_off, fwd_runs_off, fwd_tiles_off, fwd_tiles1_off, rec_tiles_off,
-        acc_off,
-        tsum_off, ab_off, C_off, fields_off, total;
+    size_t fb, runs_off, cd_off, adj_off, tiles_off, tiles1_off, fwd_runs_off, fwd_tiles_off, fwd_tiles1_off,
+        rec_tiles_off, acc_off, tsum_off, ab_off, C_off, fields_off, total;
     int tile_cap;               // tile-table entries (all shots) for any tuning
 };
 
@@ -2631,7 +2630,7 @@ extern "C" int empso_gradient(const empso_problem *p, const float *vp_d, const f
     EMPSO_HIP(hipMemcpyAsync(runs, hr.data(), sizeof(GradRun) * ns, hipMemcpyHostToDevice, st));
     GradShared sh;
     sh.C = reinterpret_cast<const float *>(w + L.C_off);
-    sh.az = p->d_az; sh.ax = p->d_ax; sh.wav = p->d_wav; sh.recmap = p->d_recmap;
+    sh.az = p->d_az; sh.ax = p->d_ax; sh.recmap = p->d_recmap;
     sh.gfs = gfs;
     sh.Nz = p->Nz; sh.Nx = p->Nx; sh.S = p->S; sh.nrec = p->g.nrec; sh.recS = p->recI + kRing; sh.nt = nt;
     sh.cz1 = p->cz[0]; sh.cz2 = p->cz[1]; sh.cz3 = p->cz[2]; sh.cz4 = p->cz[3];
