@@ -689,14 +689,14 @@ __device__ __forceinline__ float from_lane_above(float v) {
 // same reciprocal); otherwise in full. Each form is the full one with a
 // zero term, bit for bit, so the results do not depend on the tiling.
 //
-// Record mode (REC, the misfit gradient's recomputation of a segment): the
+// Level-keeping mode (KEEP, the misfit gradient's recomputation of a segment): the
 // run's fields are a segment's time levels, u^m in field m - b + 1 (b = the
 // segment's first step, fields R.fbytes apart from R.u[0]); the launch reads
 // u^n and u^{n-1} from fields n - b + 1 and n - b and stores every level's
 // owned rows, u^{n+l+1} into field n - b + 2 + l, so all T levels of the
 // launch are kept. No receivers are sampled (the descriptor's receiver row
 // is one no tile owns).
-template <int T, bool ISO, bool REC>
+template <int T, bool ISO, bool KEEP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(T < 3 ? 3 : 2))) void k_tb(const RunDesc *__restrict__ runs, const int4 *__restrict__ tiles,
                                             int ntiles, int n, int par, int b) {
     constexpr int NS = kQueue;
@@ -718,10 +718,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(T < 3 ? 3 :
     // R.u[par]: a runtime index would move R to scratch memory). Reads that
     // run past a field land in the next field's zero ring or beyond the range
     // (zero); both only feed rows that are never stored.
-    const float *fbase = REC ? R.u[0] + (size_t)(n - b) * (R.fbytes >> 2) : R.u[0];
-    const rsrc_t F = make_rsrc(fbase, (REC ? (unsigned)(T + 2) : 4u) * R.fbytes);
+    const float *fbase = KEEP ? R.u[0] + (size_t)(n - b) * (R.fbytes >> 2) : R.u[0];
+    const rsrc_t F = make_rsrc(fbase, (KEEP ? (unsigned)(T + 2) : 4u) * R.fbytes);
     const int fb = (int)R.fbytes;
-    const int uin = (REC || par) ? fb : 0, vin = REC ? 0 : (par ? 3 * fb : 2 * fb);
+    const int uin = (KEEP || par) ? fb : 0, vin = KEEP ? 0 : (par ? 3 * fb : 2 * fb);
     const int uout = par ? 0 : fb, vout = par ? 2 * fb : 3 * fb;
     const rsrc_t Cf = make_rsrc(R.C, R.fbytes);
     const int c = t.z + 4 * lane;                   // stored column of this lane's first element
@@ -860,12 +860,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(T < 3 ? 3 :
             un = make_float4(uo[0], uo[1], uo[2], uo[3]);
             ue = ce;
             if (l < T - 1) qu[l][(k + 8) % NS] = un;
-            if constexpr (REC) {
+            if constexpr (KEEP) {
                 const bool okl = own && (r >= s0) && (r < s1);
                 bst4(F, okl ? (2 + l) * fb + r * rowb + lcol : kDrop, un);
             }
         }
-        if constexpr (!REC) {
+        if constexpr (!KEEP) {
             const int rT = r1 - 4 * (T - 1);
             const bool ok = own && (rT >= s0) && (rT < s1);
             const int o = rT * rowb + lcol;
@@ -1149,8 +1149,8 @@ static int launch_tb(int T, bool iso, const RunDesc *runs, const int4 *tiles, in
     return EMPSO_ENOTSUP;
 }
 
-// Record-mode launch (steps n .. n+T-1 of a segment that starts at step b).
-static int launch_tb_rec(int T, bool iso, const RunDesc *runs, const int4 *tiles, int ntiles, int n, int b,
+// Level-keeping launch (steps n .. n+T-1 of a segment that starts at step b).
+static int launch_tb_keep(int T, bool iso, const RunDesc *runs, const int4 *tiles, int ntiles, int n, int b,
                          hipStream_t st) {
     int blocks = (ntiles + 3) / 4;
     blocks = (blocks + 7) / 8 * 8;
@@ -2565,7 +2565,7 @@ static GradLayout grad_layout(const empso_problem *p, int K) {
     L.tiles_off = take(sizeof(int4) * (size_t)L.tile_cap);
     L.tiles1_off = take(sizeof(int4) * (size_t)L.tile_cap);
     L.fwd_runs_off = take(sizeof(RunDesc) * ns * (1 + L.sl.nbuf));   // fitness-kernel passes: checkpointing,
-                                                                     // then record mode per segment buffer
+                                                                     // then level keeping per segment buffer
     L.fwd_tiles_off = take(sizeof(int4) * (size_t)L.tile_cap);
     L.fwd_tiles1_off = take(sizeof(int4) * (size_t)L.tile_cap);
     L.rec_tiles_off = take(sizeof(int4) * (size_t)L.tile_cap);
@@ -2595,7 +2595,7 @@ extern "C" int empso_gradient(const empso_problem *p, const float *vp_d, const f
     if (p->g.nt < 2) EMPSO_FAIL(EMPSO_EINVAL, "the gradient needs nt >= 2");
     if (reinterpret_cast<uintptr_t>(ws) % 256) EMPSO_FAIL(EMPSO_EINVAL, "workspace must be 256-byte aligned");
     const GradLayout L = grad_layout(p, checkpoint_every);
-    // record mode addresses kMaxT + 2 consecutive fields through one buffer
+    // level keeping addresses kMaxT + 2 consecutive fields through one buffer
     // resource with 32-bit byte offsets below 2^31 (kDrop must stay outside)
     if ((uint64_t)(kMaxT + 2) * L.fb >= ((uint64_t)1 << 31))
         EMPSO_FAIL(EMPSO_ENOTSUP, "grid too large for the gradient: a stored field takes %zu bytes (limit %llu)", L.fb,
@@ -2687,7 +2687,7 @@ extern "C" int empso_gradient(const empso_problem *p, const float *vp_d, const f
     const int nrt = tiles_of(p, rbz, rT) * ns;
     {
         // table 0: the checkpointing pass on the state fields; table 1 + buf:
-        // record mode on segment buffer buf
+        // level keeping on segment buffer buf
         std::vector<RunDesc> hf((size_t)ns * (1 + sl.nbuf));
         for (int q = 0; q <= sl.nbuf; ++q)
             for (int s = 0; s < ns; ++s) {
@@ -2848,7 +2848,7 @@ extern "C" int empso_gradient(const empso_problem *p, const float *vp_d, const f
         EMPSO_HIP(hipEventRecord(ev[0], st));
         EMPSO_HIP(hipStreamWaitEvent(st2, ev[0], 0));
     }
-    // a segment's levels by the fitness kernel in record mode (launches of T
+    // a segment's levels by the fitness kernel keeping every level (launches of T
     // steps, single steps for the rest)
     auto recompute = [&](int j, int buf, hipStream_t s) -> int {
         const int b = j * K, e = std::min((j + 1) * K, nt - 1);
@@ -2857,7 +2857,7 @@ extern "C" int empso_gradient(const empso_problem *p, const float *vp_d, const f
         const RunDesc *rr = fruns + (size_t)(1 + buf) * ns;
         for (int n = b; n < e;) {
             const int T = n + rT <= e ? rT : 1;
-            const int rc = launch_tb_rec(T, iso, rr, T == 1 ? ftiles1 : rtiles, T == 1 ? nft1 : nrt, n, b, s);
+            const int rc = launch_tb_keep(T, iso, rr, T == 1 ? ftiles1 : rtiles, T == 1 ? nft1 : nrt, n, b, s);
             if (rc) return rc;
             n += T;
         }
