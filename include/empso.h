@@ -367,11 +367,12 @@ int empso_time_tuning(const empso_problem *const *probs, int32_t nprob, const fl
  * recomputation in a mode that keeps every time level). K >= nt - 1 keeps
  * every time level of one forward pass instead (one forward and one adjoint
  * pass; nt + 9 fields per shot, e.g. 234 GB for 16 shots of 381 x 1001 points
- * over 8114 steps). The adjoint advances up to three time steps per launch
- * unless the illumination is requested, which the single-step adjoint
- * accumulates; both give the same gradient to FP32 rounding. The same pass can
- * return the source illumination sum_s sum_{n>=1} u_s^n(x)^2, folded the same
- * way, the usual diagonal scaling (pseudo-Hessian) of the gradient.
+ * over 8114 steps). The adjoint advances up to three time steps per launch.
+ * The same pass can return the source illumination
+ * sum_s sum_{n>=1} u_s^n(x)^2, summed from the recomputed levels of each
+ * segment and folded the same way, the usual diagonal scaling
+ * (pseudo-Hessian) of the gradient; asking for it changes neither the
+ * gradient nor the misfit (bit for bit).
  * ------------------------------------------------------------------------ */
 
 /* Workspace bytes for empso_gradient (0 on invalid arguments). */

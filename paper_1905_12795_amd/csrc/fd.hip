@@ -2022,14 +2022,17 @@ static int forward_autotune(const std::vector<const empso_problem *> &pp, const 
 //   (1+a) psi^k = 2 psi^{k+1} - (1-a) psi^{k+2} + C (Lap_h psi^{k+1} + r^k),
 // k = nt-1 .. 1, psi^{nt} = psi^{nt+1} = 0, and
 //   dJ/dC = sum_n psi^{n+1} [(1+a) u^{n+1} - 2 u^n + (1-a) u^{n-1}] / C^2
-// (accumulated as the same sum rearranged by parts: u^n times psi's second
-// time difference),
+// = sum_m u^m L^m / C after a summation by parts (u^0 = u^{-1} = 0 and
+// psi^{nt} = psi^{nt+1} = 0 leave no boundary terms) and the adjoint
+// recursion, with L^m = Lap_h psi^{m+1} + r^m the quantity each adjoint update
+// multiplies by C,
 //   dJ/dv = dJ/dC 2 v dt^2, folded from the padded grid onto the physical
 // model (each padded point adds into the point it copies) and summed over
 // shots. Both directions use the increment form of the fitness kernels. The
 // forward pass keeps (u^{jK}, u^{jK-1}) every K steps; the backward pass
 // restores each segment from its checkpoint, recomputes its K time levels and
-// runs the adjoint through it, accumulating the gradient as it goes.
+// runs the adjoint through it, accumulating the gradient as it goes (and, if
+// asked for, the illumination sum_n (u^n)^2 from the same recomputed levels).
 // ---------------------------------------------------------------------------
 namespace {
 
@@ -2043,26 +2046,16 @@ struct GradRun {
     int srcS, srcC;             // stored row and column of the source
 };
 
-struct GradShared {
-    const float *C, *az, *ax;
-    const int *recmap;
-    size_t gfs;                 // floats per field
-    int Nz, Nx, S, nrec, recS, nt;
-    float cz1, cz2, cz3, cz4, cx1, cx2, cx3, cx4, wscale;
-};
-
 // Field slots of a run: nbuf buffers of K+2 segment levels each (with more
 // than one segment, two buffers: the next segment is recomputed into one
 // while the adjoint runs through the other), then the four contiguous fields
-// that hold the forward state during the checkpointing pass and the adjoint
-// afterwards (two pairs for the blocked adjoint, a ring of three for the
-// single-step one), the gradient accumulator, the illumination accumulator,
-// then two fields per checkpoint.
+// that hold the forward state during the checkpointing pass and the adjoint's
+// two pairs of levels afterwards, the gradient accumulator, the illumination
+// accumulator, then two fields per checkpoint.
 struct GradSlots {
     int K, ncheck, nbuf;
     int seg(int buf, int i) const { return buf * (K + 2) + i; }
     int adjp() const { return nbuf * (K + 2); }
-    int adj(int k) const { return adjp() + ((k % 3) + 3) % 3; }
     int gacc() const { return adjp() + 4; }
     int illum() const { return adjp() + 5; }
     int ck(int j, int which) const { return adjp() + 6 + 2 * j + which; }
@@ -2074,20 +2067,6 @@ static int grad_interval(const empso_problem *p, int K) {
     return std::max(1, (int)std::ceil(std::sqrt(2.0 * std::max(1, p->g.nt - 1))));
 }
 
-// One adjoint step of every run (the single-step adjoint, used when the
-// illumination is asked for): out = cur + d with
-// d = [(1-a)(cur - prev) + C (Lap cur + s)] / (1+a), where s is the
-// derivative of the misfit with respect to u^k at the receivers, u^k - d^k
-// (l2, accumulated into the misfit) or (a u^k - b d^k) / sd (trace-normalised),
-// and the gradient accumulator takes
-// u^k [(1+a)(psi^k - psi^{k+1}) - (1-a)(psi^{k+1} - psi^{k+2})]: the imaging
-// sum over k of psi^k times u's second time difference at k, rearranged by
-// parts (u^0 = u^{-1} = 0 and psi^{nt} = psi^{nt+1} = 0, so no boundary
-// terms), which needs one stored forward level per step instead of three;
-// the illumination accumulator takes (u^k)^2.
-// Thread (x, y) of block (bx, by, run) updates columns 4 (64 bx + x) .. +3 of
-// padded row kGRows by + y.
-static constexpr int kGRows = 4;     // rows per block of k_gstep
 static constexpr int kAdjT = 3;      // adjoint steps per launch of k_tba
 static constexpr int kAdjBz = 40;    // its tile height (measured best with the overlapped recomputation)
 // tile height and depth of the checkpointing pass (measured on 16 realistic
@@ -2099,83 +2078,6 @@ static constexpr int kGradFwdT = 2;
 // with the adjoint (0: those of the checkpointing pass)
 static constexpr int kGradRecBz = 40;
 static constexpr int kGradRecT = 4;
-template <bool ISO>
-__global__ __launch_bounds__(64 * kGRows) void k_gstep(const GradRun *__restrict__ runs, const GradShared sh, int cur,
-                                               int prev, int out, int k, int uk, int gacc, int illum) {
-    const int I = blockIdx.y * kGRows + (int)threadIdx.y;
-    const int J0 = 4 * (blockIdx.x * 64 + (int)threadIdx.x);
-    if (I >= sh.Nz || J0 >= sh.Nx) return;
-    const GradRun R = runs[blockIdx.z];
-    const int s = I + kRing, c = J0 + kRing;
-    const size_t o = (size_t)s * sh.S + c;
-    const float *Fc = R.fields + (size_t)cur * sh.gfs;
-    const float *Fp = R.fields + (size_t)prev * sh.gfs;
-    auto ld4 = [&](const float *F, size_t off) { return *reinterpret_cast<const float4 *>(F + off); };
-    const float4 cl = ld4(Fc, o - 4), cc = ld4(Fc, o), cr = ld4(Fc, o + 4);
-    const float v[12] = {cl.x, cl.y, cl.z, cl.w, cc.x, cc.y, cc.z, cc.w, cr.x, cr.y, cr.z, cr.w};
-    float4 zp[4], zm[4];
-#pragma unroll
-    for (int m = 1; m <= 4; ++m) {
-        zm[m - 1] = ld4(Fc, o - (size_t)m * sh.S);
-        zp[m - 1] = ld4(Fc, o + (size_t)m * sh.S);
-    }
-    const float4 pv4 = ld4(Fp, o), C4 = ld4(sh.C, o);
-    const float pv[4] = {pv4.x, pv4.y, pv4.z, pv4.w}, Cv[4] = {C4.x, C4.y, C4.z, C4.w};
-    const float cz[4] = {sh.cz1, sh.cz2, sh.cz3, sh.cz4}, cx[4] = {sh.cx1, sh.cx2, sh.cx3, sh.cx4};
-    const float azr = sh.az[I];
-    const float4 Uk4 = ld4(R.fields + (size_t)uk * sh.gfs, o);
-    const float ukv[4] = {Uk4.x, Uk4.y, Uk4.z, Uk4.w};
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const float u = v[4 + q];
-        const float zs[4] = {(&zp[3].x)[q] + (&zm[3].x)[q], (&zp[2].x)[q] + (&zm[2].x)[q],
-                             (&zp[1].x)[q] + (&zm[1].x)[q], (&zp[0].x)[q] + (&zm[0].x)[q]};
-        const float xs[4] = {v[q] + v[8 + q], v[1 + q] + v[7 + q], v[2 + q] + v[6 + q], v[3 + q] + v[5 + q]};
-        float lap;
-        if (ISO) {
-            lap = cz[3] * (zs[0] + xs[0]);
-            lap = fmaf(cz[2], fmaf(-kFold3, u, zs[1] + xs[1]), lap);
-            lap = fmaf(cz[1], fmaf(-4.0f, u, zs[2] + xs[2]), lap);
-            lap = fmaf(cz[0], fmaf(-4.0f, u, zs[3] + xs[3]), lap);
-        } else {
-            lap = cz[3] * zs[0];
-            lap = fmaf(cz[2], fmaf(-kFold3Axis, u, zs[1]), lap);
-            lap = fmaf(cz[1], fmaf(-2.0f, u, zs[2]), lap);
-            lap = fmaf(cz[0], fmaf(-2.0f, u, zs[3]), lap);
-            lap = fmaf(cx[3], xs[0], lap);
-            lap = fmaf(cx[2], fmaf(-kFold3Axis, u, xs[1]), lap);
-            lap = fmaf(cx[1], fmaf(-2.0f, u, xs[2]), lap);
-            lap = fmaf(cx[0], fmaf(-2.0f, u, xs[3]), lap);
-        }
-        const int J = J0 + q;
-        if (s == sh.recS && J < sh.Nx) {
-            const int r = sh.recmap[J];
-            if (r >= 0) {
-                const float ob = R.obs[(size_t)k * sh.nrec + r];
-                float res;
-                if (R.ab) {
-                    res = fmaf(R.ab[r], ukv[q], -R.ab[sh.nrec + r] * ob) * R.ab[2 * sh.nrec + r];
-                } else {
-                    res = ukv[q] - ob;
-                    R.acc[r] += (double)res * (double)res;
-                }
-                lap += res;
-            }
-        }
-        const float a = azr + ((J < sh.Nx) ? sh.ax[J] : 0.0f);
-        const float d = fmaf(Cv[q], lap, (1.0f - a) * (u - pv[q])) * __builtin_amdgcn_rcpf(1.0f + a);
-        const float un = u + d;
-        R.fields[(size_t)out * sh.gfs + o + q] = un;
-        const float u0 = ukv[q];
-        float *g = R.fields + (size_t)gacc * sh.gfs + o + q;
-        *g = fmaf(u0, (1.0f + a) * (un - u) - (1.0f - a) * (u - pv[q]), *g);
-        if (illum) {
-            float *il = R.fields + (size_t)(gacc + 1) * sh.gfs + o + q;  // illumination: sum of u^k^2
-            *il = fmaf(u0, u0, *il);
-        }
-    }
-}
-
 // Adjoint of one run (shot) for the temporally blocked adjoint kernel.
 struct AdjDesc {
     float *psi;                 // four contiguous fields; pair p holds (psi^{k+1}, psi^{k+2}) in fields p, 2 + p
@@ -2426,30 +2328,50 @@ __global__ void k_gcopy(const GradRun *__restrict__ runs, size_t gfs, int src, i
         b[i] = a[i];
 }
 
+// Illumination of one segment: acc += (u^k)^2 at every stored point of every
+// run for k = lo + n - 1 down to lo (the adjoint's order of time steps), u^k
+// in field slot first + k - lo.
+__global__ void k_gillum(const GradRun *__restrict__ runs, size_t gfs, int first, int n, int acc) {
+    const GradRun R = runs[blockIdx.y];
+    const size_t n4 = gfs / 4;
+    const float4 *u = reinterpret_cast<const float4 *>(R.fields + (size_t)first * gfs);
+    float4 *a = reinterpret_cast<float4 *>(R.fields + (size_t)acc * gfs);
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += (size_t)gridDim.x * blockDim.x) {
+        float4 sum = a[i];
+        for (int m = n - 1; m >= 0; --m) {
+            const float4 x = u[(size_t)m * n4 + i];
+            sum.x = fmaf(x.x, x.x, sum.x);
+            sum.y = fmaf(x.y, x.y, sum.y);
+            sum.z = fmaf(x.z, x.z, sum.z);
+            sum.w = fmaf(x.w, x.w, sum.w);
+        }
+        a[i] = sum;
+    }
+}
+
 // Physical gradient: each physical point gathers the padded points that copy
 // it (its own, plus the absorbing-layer strip or corner beyond an edge), over
-// all runs in a fixed order, times 2 / (v^3 dt^2) or 2 / v (by_L).
-__global__ void k_gfold(const GradRun *__restrict__ runs, int nruns, const GradShared sh, int gacc, const float *vp,
-                        int nz, int nx, int nbl, double dt, int by_L, float *grad, float *illum) {
+// all runs in a fixed order, times 2 / v (the accumulator holds dJ/dC times C,
+// and dJ/dv = dJ/dC 2 v dt^2 with C = (v dt)^2); the illumination accumulator
+// (slot gacc + 1), if asked for, is gathered the same way.
+__global__ void k_gfold(const GradRun *__restrict__ runs, int nruns, size_t gfs, int Nz, int Nx, int S, int gacc,
+                        const float *vp, int nz, int nx, int nbl, float *grad, float *illum) {
     const int64_t n = (int64_t)nz * nx;
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
         const int i = (int)(q / nx), j = (int)(q - (int64_t)i * nx);
-        const int I0 = i == 0 ? 0 : i + nbl, I1 = i == nz - 1 ? sh.Nz - 1 : i + nbl;
-        const int J0 = j == 0 ? 0 : j + nbl, J1 = j == nx - 1 ? sh.Nx - 1 : j + nbl;
+        const int I0 = i == 0 ? 0 : i + nbl, I1 = i == nz - 1 ? Nz - 1 : i + nbl;
+        const int J0 = j == 0 ? 0 : j + nbl, J1 = j == nx - 1 ? Nx - 1 : j + nbl;
         double sum = 0.0, ill = 0.0;
         for (int r = 0; r < nruns; ++r) {
-            const float *g = runs[r].fields + (size_t)gacc * sh.gfs;
-            const float *h = g + sh.gfs;
+            const float *g = runs[r].fields + (size_t)gacc * gfs;
+            const float *h = g + gfs;
             for (int I = I0; I <= I1; ++I)
                 for (int J = J0; J <= J1; ++J) {
-                    sum += (double)g[(size_t)(I + kRing) * sh.S + J + kRing];
-                    if (illum) ill += (double)h[(size_t)(I + kRing) * sh.S + J + kRing];
+                    sum += (double)g[(size_t)(I + kRing) * S + J + kRing];
+                    if (illum) ill += (double)h[(size_t)(I + kRing) * S + J + kRing];
                 }
         }
-        const double v = vp[q];
-        // the accumulator holds dJ/dC times C^2 (single-step adjoint) or times
-        // C (blocked adjoint); dJ/dv = dJ/dC 2 v dt^2 with C = (v dt)^2
-        grad[q] = (float)(by_L ? sum * 2.0 / v : sum * 2.0 / (v * v * v * dt * dt));
+        grad[q] = (float)(sum * 2.0 / (double)vp[q]);
         if (illum) illum[q] = (float)ill;
     }
 }
@@ -2628,14 +2550,7 @@ extern "C" int empso_gradient(const empso_problem *p, const float *vp_d, const f
     // stream-ordered uploads (the caller's earlier work on st may still read
     // the workspace), waited for before the host copies go
     EMPSO_HIP(hipMemcpyAsync(runs, hr.data(), sizeof(GradRun) * ns, hipMemcpyHostToDevice, st));
-    GradShared sh;
-    sh.C = reinterpret_cast<const float *>(w + L.C_off);
-    sh.az = p->d_az; sh.ax = p->d_ax; sh.recmap = p->d_recmap;
-    sh.gfs = gfs;
-    sh.Nz = p->Nz; sh.Nx = p->Nx; sh.S = p->S; sh.nrec = p->g.nrec; sh.recS = p->recI + kRing; sh.nt = nt;
-    sh.cz1 = p->cz[0]; sh.cz2 = p->cz[1]; sh.cz3 = p->cz[2]; sh.cz4 = p->cz[3];
-    sh.cx1 = p->cx[0]; sh.cx2 = p->cx[1]; sh.cx3 = p->cx[2]; sh.cx4 = p->cx[3];
-    sh.wscale = p->wscale;
+    const float *Cf = reinterpret_cast<const float *>(w + L.C_off);
     const bool iso = p->g.dz == p->g.dx;
 
     // clear the fields and accumulators, then the coefficient field of vp
@@ -2652,14 +2567,7 @@ extern "C" int empso_gradient(const empso_problem *p, const float *vp_d, const f
     EMPSO_HIP(hipStreamSynchronize(st));
     k_coef<<<dim3(1024, 1), 256, 0, st>>>(cdd);
 
-    const dim3 blk(64, kGRows), grd((p->Nx + 255) / 256, (p->Nz + kGRows - 1) / kGRows, ns);
     const int cblocks = (int)std::min<size_t>(4096, (gfs / 4 + 255) / 256);
-    auto step_adj = [&](int k, int cur, int prev, int out, int uk) {
-        if (iso)
-            k_gstep<true><<<grd, blk, 0, st>>>(runs, sh, cur, prev, out, k, uk, sl.gacc(), illum_d != nullptr);
-        else
-            k_gstep<false><<<grd, blk, 0, st>>>(runs, sh, cur, prev, out, k, uk, sl.gacc(), illum_d != nullptr);
-    };
     auto copy = [&](hipStream_t s, int src, int dst) {
         k_gcopy<<<dim3(cblocks, ns), 256, 0, s>>>(runs, gfs, src, dst);
     };
@@ -2667,9 +2575,7 @@ extern "C" int empso_gradient(const empso_problem *p, const float *vp_d, const f
     // Tables of the checkpointing pass, which runs the fitness kernel on the
     // four state fields (no receivers with the l2 misfit; the trace sums of
     // the trace-normalised one), and of the blocked adjoint (k_tba, T adjoint
-    // steps per launch; one descriptor table per segment buffer), unless the
-    // illumination is asked for, which the single-step adjoint accumulates.
-    const bool blocked = illum_d == nullptr;
+    // steps per launch; one descriptor table per segment buffer).
     const int Ta = kAdjT, bza = kAdjBz;
     std::vector<const empso_problem *> pp(1, p);
     std::vector<RunSpec> rsp;
@@ -2695,7 +2601,7 @@ extern "C" int empso_gradient(const empso_problem *p, const float *vp_d, const f
                 d = RunDesc{};
                 float *f = hr[s].fields + (size_t)(q == 0 ? sl.adjp() : sl.seg(q - 1, 0)) * gfs;
                 d.u[0] = f; d.u[1] = f + gfs; d.v[0] = f + 2 * gfs; d.v[1] = f + 3 * gfs;
-                d.C = sh.C;
+                d.C = Cf;
                 const bool sums = norm && q == 0;
                 d.obs = sums ? hr[s].obs : nullptr;
                 d.traces = nullptr;
@@ -2731,13 +2637,13 @@ extern "C" int empso_gradient(const empso_problem *p, const float *vp_d, const f
     AdjDesc *adjd = reinterpret_cast<AdjDesc *>(w + L.adj_off);
     int4 *tdA = reinterpret_cast<int4 *>(w + L.tiles_off), *tdA1 = reinterpret_cast<int4 *>(w + L.tiles1_off);
     int ntA = 0, ntA1 = 0;
-    if (blocked) {
+    {
         std::vector<AdjDesc> ha((size_t)ns * sl.nbuf);
         for (int buf = 0; buf < sl.nbuf; ++buf)
             for (int s = 0; s < ns; ++s) {
                 AdjDesc &a = ha[(size_t)buf * ns + s];
                 a.psi = hr[s].fields + (size_t)sl.adjp() * gfs;
-                a.C = sh.C;
+                a.C = Cf;
                 a.seg = hr[s].fields + (size_t)sl.seg(buf, 0) * gfs;
                 a.g = hr[s].fields + (size_t)sl.gacc() * gfs;
                 a.obs = hr[s].obs;
@@ -2874,22 +2780,19 @@ extern "C" int empso_gradient(const empso_problem *p, const float *vp_d, const f
             EMPSO_HIP(hipEventRecord(ev[1 + nb], st2));
         }
         if (j < last) EMPSO_HIP(hipStreamWaitEvent(st, ev[1 + buf], 0));
-        if (blocked) {
-            for (int k = e; k >= b + 1; apar ^= 1) {
-                const int T = (k - Ta + 1 >= b + 1) ? Ta : 1;
-                launch_adj(T, k, b, apar, buf);
-                k -= T;
-            }
-        } else {
-            for (int k = e; k >= b + 1; --k)
-                step_adj(k, sl.adj(k + 1), sl.adj(k + 2), sl.adj(k), sl.seg(buf, k - b + 1));
+        for (int k = e; k >= b + 1; apar ^= 1) {
+            const int T = (k - Ta + 1 >= b + 1) ? Ta : 1;
+            launch_adj(T, k, b, apar, buf);
+            k -= T;
         }
+        // the illumination of u^{b+1} .. u^e (slots 2 .. e - b + 1), before the
+        // buffer is released to the next recomputation
+        if (illum_d) k_gillum<<<dim3(cblocks, ns), 256, 0, st>>>(runs, gfs, sl.seg(buf, 2), e - b, sl.illum());
         if (sl.nbuf == 2) EMPSO_HIP(hipEventRecord(ev[3 + buf], st));
     }
     const int64_t npts = (int64_t)p->g.nz * p->g.nx;
-    k_gfold<<<(int)std::min<int64_t>(2048, (npts + 255) / 256), 256, 0, st>>>(runs, ns, sh, sl.gacc(), vp_d, p->g.nz,
-                                                                              p->g.nx, p->g.nbl, p->g.dt, blocked ? 1 : 0,
-                                                                              grad_d, illum_d);
+    k_gfold<<<(int)std::min<int64_t>(2048, (npts + 255) / 256), 256, 0, st>>>(
+        runs, ns, gfs, p->Nz, p->Nx, p->S, sl.gacc(), vp_d, p->g.nz, p->g.nx, p->g.nbl, grad_d, illum_d);
     k_gmisfit<<<1, 256, 0, st>>>(runs, ns, p->g.nrec, norm ? 1 : 0, misfit_d);
     EMPSO_HIP(hipGetLastError());
     return EMPSO_OK;
