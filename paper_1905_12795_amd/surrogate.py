@@ -5,10 +5,12 @@ FP32 accumulation, FP32 Adam) learns the standardised log-misfit of
 control-node vectors from the (particle, misfit) pairs that the
 finite-difference fitness produces during the search. Before each
 finite-difference evaluation, every particle proposes several candidate
-moves (independent draws of Eq. 1's random vectors); the network ranks them
-and only each particle's best-ranked candidate is evaluated, so the number of
-finite-difference evaluations per iteration is unchanged while the moves that
-reach the solver are better on average.
+moves (independent draws of Eq. 1's random vectors) and takes the one the
+network ranks best. Either every particle is then evaluated (the number of
+finite-difference evaluations per iteration is unchanged, the moves that
+reach the solver are better on average), or only the M particles whose new
+positions rank best across the swarm are (the global screen: N K candidates
+ranked, M finite-difference evaluations per iteration).
 """
 import ctypes
 
