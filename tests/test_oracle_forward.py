@@ -194,3 +194,35 @@ def test_causality_exact_zeros():
 def test_zero_damping_inside_physical_domain():
     d = fd.damping_profile(50, 70, 20, 10.0, 10.0, 6000.0, 1e-3)
     assert np.all(d[20:70, 20:90] == 0.0)
+
+
+def _box_geom(nz, nx, si, sj, offs, h=10.0):
+    """Homogeneous-medium geometry without an absorbing layer: one source at
+    grid point (si, sj), receivers at the given (row, column) offsets from it."""
+    return {"nz": nz, "nx": nx, "dz": h, "dx": h, "nbl": 0, "vmax": 2500.0, "f0": 100.0,
+            "src": [[si * h, sj * h]], "rec": [[(si + a) * h, (sj + b) * h] for a, b in offs]}
+
+
+def test_grid_beyond_the_records_reach_leaves_the_traces_bit_for_bit():
+    """A field that starts at the source is nonzero at step n only within
+    ceil(di/4) + ceil(dj/4) <= n - 1 of it, so two grids that agree on the
+    region the record reaches give identical traces whatever lies beyond: a
+    source 60 points from every edge of a 121 x 121 grid, and the same source
+    60 points from the bottom and right edges of a 191 x 233 grid."""
+    offs = [(-6, dj) for dj in range(-12, 13, 3)]
+    dt = 0.4 * fd.stable_dt(2500.0, 10.0, 10.0)
+    nt = 17                                   # u^16: ceil(61/4) = 16 steps from the source, not beyond
+    small = fd.Problem(_box_geom(121, 121, 60, 60, offs), dt=dt, nt=nt)
+    big = fd.Problem(_box_geom(191, 233, 130, 172, offs), dt=dt, nt=nt)
+    ts = fd.forward_shots(small, np.full((121, 121), 2000.0))
+    tb = fd.forward_shots(big, np.full((191, 233), 2000.0))
+    assert np.max(np.abs(ts)) > 0
+    assert np.array_equal(ts, tb)
+    # a velocity change at the source changes the traces; one just beyond
+    # the field's reach does not
+    vin = np.full((191, 233), 2000.0)
+    vin[130, 172] = 2100.0
+    vout = np.full((191, 233), 2000.0)
+    vout[130, 172 - 61] = 2100.0
+    assert not np.array_equal(fd.forward_shots(big, vin), tb)
+    assert np.array_equal(fd.forward_shots(big, vout), tb)
