@@ -1,4 +1,4 @@
-"""The largest grid the library accepts, against a small grid and the oracle (run on an MI355X).
+"""The largest grids the library accepts, against small grids and the oracle (run on an MI355X).
 
 The stencil kernel addresses a run's four stored fields through one buffer
 resource with 32-bit byte offsets, so a stored field may take at most 2^29
@@ -89,3 +89,51 @@ def test_largest_accepted_grid_equals_a_small_grid_by_causality():
     assert abs(fg - float(fo[0])) <= REL * float(fo[0])
     del fb
     torch.cuda.empty_cache()
+
+
+def test_largest_gradient_grid_equals_a_small_grid_by_causality():
+    """The gradient's segment recomputation addresses six consecutive stored
+    fields through one buffer resource, so its stored field stays below
+    2^31 / 6 bytes: 10890 x 8160 points without a layer (10922 stored rows of
+    8192 floats, 357,892,096 bytes) is its largest grid of that width. With
+    the source 300 points from the bottom and right edges and receivers
+    within 6 rows and 8 columns of it, neither the forward field nor the
+    adjoint field (which starts at the receivers) reaches 300 points from the
+    source in 60 samples, so the misfit and the gradient equal those of a
+    601 x 601 grid with the source at its centre bit for bit (the gradient
+    zero elsewhere), at two checkpoint intervals; the small grid's gradient
+    is held to 1e-3 of the oracle's."""
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    from paper_1905_12795_amd import fd as gfd
+    dt = 0.4 * ofd.stable_dt(2500.0, H, H)
+    offs = [(-6, dj) for dj in range(-8, 9, 2)]
+
+    def geom(nz, nx, si, sj):
+        g = _geom(nz, nx, si, sj)
+        g["rec"] = [[(si + a) * H, (sj + b) * H] for a, b in offs]
+        return g
+
+    NZ, NX, M = 10890, 8160, 601
+    small = geom(M, M, 300, 300)
+    big = geom(NZ, NX, NZ - 1 - 300, NX - 1 - 300)
+    op = ofd.Problem(small, dt=dt, nt=NT)
+    gs = gfd.Problem(small, dt=dt, nt=NT)
+    gb = gfd.Problem(big, dt=dt, nt=NT)
+    d = ofd.forward_shots(op, np.full((M, M), 2100.0))
+    J, gref = ofd.gradient(op, np.full((M, M), 2000.0), d)
+    dt_ = torch.tensor(d.astype(np.float32), device="cuda")
+    ms, grs = gfd.gradient(gs, torch.full((M, M), 2000.0, device="cuda"), dt_)
+    e = float(np.linalg.norm(grs.cpu().numpy() - gref) / np.linalg.norm(gref))
+    _say("gradient, small grid against the oracle: misfit", float(ms), J, "gradient rel L2", e)
+    assert abs(float(ms) - J) <= REL * J and e <= 1e-3
+    vb = torch.full((NZ, NX), 2000.0, device="cuda")
+    for K in (0, 7):
+        mb, grb = gfd.gradient(gb, vb, dt_, checkpoint_every=K)
+        torch.cuda.synchronize()
+        corner = grb[NZ - M:, NX - M:]
+        same = bool(torch.equal(mb, ms)) and bool(torch.equal(corner, grs))
+        rest = float(grb.abs().sum()) - float(corner.abs().sum())
+        _say("largest gradient grid, checkpoint interval", K, "bitwise equal:", same, "outside:", rest)
+        assert same and rest == 0.0, K
+        del mb, grb, corner
+        torch.cuda.empty_cache()
