@@ -199,3 +199,53 @@ def test_five_training_steps_follow_the_oracle(sur):
                   % (cos_all, int(big.sum()), big.size), flush=True)
             assert big.sum() > 0
             assert cos >= 0.99, (k, which, cos)
+
+
+# Edge shapes: one row, the full workload's 160 control nodes, and the
+# largest batch the library accepts.
+@pytest.mark.parametrize("D,H,n", [(160, 256, 1), (160, 256, 33)])
+def test_forward_matches_oracle_at_edge_shapes(sur, D, H, n):
+    lo, hi, X, _ = _case(D, H, n, 5)
+    net = sur.MLP(lo, hi, H=H, seed=6)
+    y = net.predict(torch.tensor(X, dtype=torch.float32, device="cuda")).cpu().numpy()
+    yo, _ = omlp.forward(_oracle_layers(net, sur), X, lo.astype(np.float32).astype(np.float64),
+                         hi.astype(np.float32).astype(np.float64))
+    rel = np.linalg.norm(y - yo) / np.linalg.norm(yo)
+    assert rel <= 2e-2, rel
+
+
+@pytest.mark.parametrize("D,H,n", [(160, 256, 1), (160, 256, 33)])
+def test_gradient_matches_oracle_at_edge_shapes(sur, D, H, n):
+    lo, hi, X, fit = _case(D, H, n, 7)
+    net = sur.MLP(lo, hi, H=H, seed=8)
+    lf = np.log(fit.astype(np.float64))
+    mu, sigma = float(lf.mean()), float(lf.std()) if n > 1 else 1.0
+    loss, g = net.grad(torch.tensor(X, dtype=torch.float32, device="cuda"), torch.tensor(fit, device="cuda"),
+                       None, mu, sigma)
+    t = (lf - np.float32(mu)) / np.float32(sigma)
+    lo_, hi_ = lo.astype(np.float32).astype(np.float64), hi.astype(np.float32).astype(np.float64)
+    lo_ref, gr = omlp.loss_and_grads(_oracle_layers(net, sur), X, t, lo_, hi_)
+    assert abs(float(loss.item()) - lo_ref) <= 2e-2 * lo_ref
+    gg = sur.unflatten_params(g.cpu().numpy(), D, H)
+    for (gW, gb), (oW, ob) in zip(gg, gr):
+        for a, b in ((gW, oW), (gb, ob)):
+            a, b = np.ravel(a), np.ravel(b)
+            cos = float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b)))
+            assert cos >= 0.99, (n, cos)
+
+
+def test_predictions_are_row_local_up_to_the_largest_batch(sur):
+    """Every output row depends on its input row only, so a batch of the
+    largest accepted size (2^22 rows) that repeats 1000 rows predicts each of
+    them bit for bit as the 1000-row batch does."""
+    D, H, n0, n = 60, 256, 1000, 1 << 22
+    lo, hi, X0, _ = _case(D, H, n0, 9)
+    net = sur.MLP(lo, hi, H=H, seed=10)
+    x0 = torch.tensor(X0, dtype=torch.float32, device="cuda")
+    y0 = net.predict(x0)
+    idx = torch.arange(n, device="cuda") % n0
+    y = net.predict(x0[idx].contiguous())
+    assert torch.equal(y, y0[idx])
+    del y, idx
+    net._ws.clear()
+    torch.cuda.empty_cache()

@@ -166,3 +166,18 @@ def test_geometry_struct_matches_the_header(L):
     assert names == [f for f, _ in L.Geometry._fields_]
     assert (L.MISFITS["l2"], L.MISFITS["trace_normalised"]) == (0, 1)
     assert "#define EMPSO_MISFIT_L2 0" in hdr and "#define EMPSO_MISFIT_TRACE_NORMALISED 1" in hdr
+
+
+def test_mlp_shape_limits_on_the_host(L):
+    """The network's shape bounds (1 <= D, H <= 4096, 1 <= n <= 2^22) are checked
+    before anything reaches the device: sizes outside them have no workspace,
+    and the calls refuse them with EINVAL."""
+    ok = L.lib.empso_mlp_workspace_bytes(60, 256, 1 << 22)
+    assert ok > 0 and ok % 256 == 0
+    assert L.lib.empso_mlp_workspace_bytes(60, 256, 1) > 0
+    for D, H, n in ((60, 256, (1 << 22) + 1), (60, 256, 0), (0, 256, 8), (4097, 256, 8), (60, 4097, 8), (60, 0, 8)):
+        assert L.lib.empso_mlp_workspace_bytes(D, H, n) == 0, (D, H, n)
+    p = ctypes.c_void_p(256)                        # never dereferenced: the shape check comes first
+    assert L.lib.empso_mlp_predict(60, 256, p, p, p, p, p, (1 << 22) + 1, p, p, 1 << 40, None) == -1
+    assert b"bad shape" in L.lib.empso_last_error()
+    assert L.lib.empso_mlp_param_count(60, 256) == 256 * 60 + 256 + 2 * (256 * 256 + 256) + 256 + 1
