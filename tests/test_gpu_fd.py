@@ -444,3 +444,59 @@ def test_new_problem_after_a_destroyed_one_gets_a_fresh_plan(gfd):
     n2 = float(np.sum(dobs.astype(np.float64) ** 2))
     for k in range(4):
         assert _fit_close(float(fg[k]), fo[k], n2), (k, fg[k], fo[k])
+
+
+@pytest.mark.parametrize("nz,nx,nbl", [(2, 2, 0), (3, 5, 1), (2, 9, 0), (9, 2, 2)])
+@pytest.mark.parametrize("nt", [1, 2, 3, 5, 6, 9])
+def test_smallest_grids_and_shortest_records_match_oracle(gfd, nz, nx, nbl, nt):
+    """Grids of 2 to 9 points a side (with and without a layer) and records of
+    1 to 9 samples: fewer steps than one temporal block, a remainder after
+    whole blocks, and no step at all (nt = 1: the trace is u^0 = 0 and the
+    misfit is half the observed data's energy). Traces within 2e-4 of the
+    oracle (exactly zero where the oracle's are), bit for bit the same at
+    every depth, and the fitness of three particles, in one call and in
+    blocks of time steps, against the oracle's with random observed data."""
+    g = copy.deepcopy(config("tiny"))
+    g.update(nz=nz, nx=nx, nbl=nbl, f0=25.0, ncz=2, ncx=2)
+    g["src"] = [[0.0, 0.0], [(nz - 1) * 10.0, (nx - 1) * 10.0]]
+    g["rec"] = [[0.0, 10.0 * j] for j in range(nx)]
+    g["node_lo"], g["node_hi"] = np.full(4, 1400.0), np.full(4, 2700.0)
+    op = ofd.Problem(g, nt=nt)
+    gp = gfd.Problem(g, dt=op.dt, nt=nt)
+    rng = np.random.default_rng(nz * 100 + nx * 10 + nt)
+    vp = ofd.vp_from_nodes(rng.uniform(1500, 2600, 4), 2, 2, nz, nx)
+    to = ofd.forward_shots(op, vp)
+    vt = torch.tensor(vp, dtype=torch.float32, device="cuda")
+    ref = None
+    for T in (1, 2, 3, 4):
+        tu = gfd.default_tuning()
+        tu.bz, tu.tsteps = 20, T
+        tg = gfd.forward_shots(gp, vt, tuning=tu)
+        if ref is None:
+            ref = tg
+            t = tg.cpu().numpy()
+            n0 = float(np.linalg.norm(to))
+            if n0 == 0.0:
+                assert nt == 1 and not np.any(t), (nt, np.abs(t).max())
+            else:
+                assert float(np.linalg.norm(t - to)) <= REL * n0
+        else:
+            assert torch.equal(tg, ref), T
+    dobs = rng.standard_normal((2, nt, nx)).astype(np.float32) * np.float32(max(1e-3, np.abs(to).max()))
+    X = rng.uniform(1400, 2700, (3, 4))
+    fo, _ = ofd.fitness_batch(op, X.astype(np.float32).astype(np.float64), dobs)
+    n2 = float(np.sum(dobs.astype(np.float64) ** 2))
+    fb = gfd.FitnessBatch([gp], [torch.tensor(dobs, device="cuda")], [0] * 3)
+    f1 = fb(X).clone()
+    for k in range(3):
+        assert _fit_close(float(f1[k]), fo[k], n2), (k, float(f1[k]), fo[k])
+    if nt == 1:
+        assert np.allclose(fo, 0.5 * n2, rtol=1e-12)
+    tu = gfd.default_tuning()
+    tu.bz, tu.tsteps = 20, 2
+    f2 = fb.steps(X, 0, min(2, nt - 1), tuning=tu)
+    if nt - 1 > 2:
+        f2 = fb.steps(None, 2, nt - 1, tuning=tu)
+    f2 = f2.clone()                                  # the one-call evaluation writes the same output
+    assert torch.equal(f2, fb(X, tuning=tu)), nt
+    assert torch.equal(f2, f1), nt                   # and every tuning gives the same bits
