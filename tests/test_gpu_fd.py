@@ -154,6 +154,30 @@ def test_tiling_graph_and_repeat_are_bitwise_invariant(gfd):
         assert torch.equal(o, outs[0][1]), key
 
 
+def test_graph_replays_follow_new_particles(gfd):
+    """The captured launch sequence reads the particles' coefficient fields
+    from the workspace header that every call uploads first, so replays with
+    other particles, separated by unrelated eager work and synchronisations,
+    give each particle set's eager (uncaptured) fitness bit for bit."""
+    g = _small_geom()
+    op, gp = _pair(gfd, g)
+    rng = np.random.default_rng(21)
+    dobs = torch.tensor(rng.standard_normal((3, gp.nt, gp.nrec)).astype(np.float32) * 1e-3, device="cuda")
+    sets = [rng.uniform(1400, 2700, (5, 12)) for _ in range(3)]
+    fb = gfd.FitnessBatch([gp], [dobs], [0] * 5)
+    eager, graph = gfd.default_tuning(), gfd.default_tuning()
+    eager.use_graph, graph.use_graph = 0, 1
+    want = [fb(X, tuning=eager).clone() for X in sets]
+    assert not torch.equal(want[0], want[1])
+    a = torch.randn(512, 512, device="cuda")
+    for k in (0, 1, 2, 1, 0, 2, 2, 0):
+        got = fb(sets[k], tuning=graph).clone()
+        b = (a @ a).sum()                       # unrelated eager work between the replays
+        torch.cuda.synchronize()
+        assert torch.isfinite(b)
+        assert torch.equal(got, want[k]), k
+
+
 def test_fitness_in_time_blocks_equals_one_call(gfd):
     """An evaluation run in blocks of time steps (empso_fitness_batch_steps)
     gives the one-call fitness bit for bit, for several depths and block
