@@ -399,6 +399,9 @@ int empso_gradient(const empso_problem *prob, const float *vp_d, const float *ob
  * h = GELU(W h + b) of width H (exact erf GELU); y = w4 . h3 + b4.
  * BF16 operands on MFMA with FP32 accumulation; FP32 master parameters and
  * Adam moments. All buffers are caller-owned device memory.
+ * Shapes: 1 <= D, H <= 4096 and 1 <= n <= 2^22 rows; outside these bounds
+ * the workspace size is 0 and every call returns EMPSO_EINVAL before it
+ * touches any buffer.
  *
  * FP32 parameter layout (empso_mlp_param_count floats):
  *   W1 [H][D] | b1 [H] | W2 [H][H] | b2 [H] | W3 [H][H] | b3 [H] | w4 [H] | b4 [1]
