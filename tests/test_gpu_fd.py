@@ -524,3 +524,33 @@ def test_smallest_grids_and_shortest_records_match_oracle(gfd, nz, nx, nbl, nt):
     f2 = f2.clone()                                  # the one-call evaluation writes the same output
     assert torch.equal(f2, fb(X, tuning=tu)), nt
     assert torch.equal(f2, f1), nt                   # and every tuning gives the same bits
+
+
+@pytest.mark.parametrize("misfit", ["l2", "trace_normalised"])
+def test_non_finite_observed_data_give_infinite_fitness(gfd, misfit):
+    """A NaN or an infinity in one problem's observed data makes the fitness
+    of every particle evaluated on that problem +inf (never a best), while
+    the particles of the other problem in the same batch keep their values
+    bit for bit."""
+    g = dict(_small_geom(), misfit=misfit)
+    h = copy.deepcopy(g)
+    h["src"] = h["src"][:2]
+    _, gp = _pair(gfd, g)
+    _, hp = _pair(gfd, h)
+    rng = np.random.default_rng(41)
+    dg = rng.standard_normal((3, gp.nt, gp.nrec)).astype(np.float32) * 1e-3
+    dh = rng.standard_normal((2, hp.nt, hp.nrec)).astype(np.float32) * 1e-3
+    X = rng.uniform(1400, 2700, (6, 12))
+    pop = [0, 1, 0, 1, 1, 0]
+    ref = gfd.FitnessBatch([gp, hp], [torch.tensor(dg, device="cuda"), torch.tensor(dh, device="cuda")], pop)(X)
+    ref = ref.clone()
+    assert torch.isfinite(ref).all()
+    for bad in (np.nan, np.inf, -np.inf):
+        d = dh.copy()
+        d[1, hp.nt // 2, 7] = bad
+        out = gfd.FitnessBatch([gp, hp], [torch.tensor(dg, device="cuda"), torch.tensor(d, device="cuda")], pop)(X)
+        for k, q in enumerate(pop):
+            if q == 1:
+                assert float(out[k]) == np.inf, (bad, k, float(out[k]))
+            else:
+                assert torch.equal(out[k], ref[k]), (bad, k)
