@@ -68,7 +68,7 @@ def invert(prob, obs, vp0, iterations, vmin=None, vmax=None, first_step=20.0, ar
             y = P * (g - g_prev)
             sy = float(np.sum(s * y))
             if sy > 0:
-                alpha = float(np.sum(s * s)) / sy                 # BB1 in the metric of P
+                alpha = float(np.sum(s * s)) / sy                 # BB1 on the preconditioned gradient P g
         trials = 0
         while True:
             trials += 1
