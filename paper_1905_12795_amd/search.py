@@ -92,7 +92,10 @@ def run(geom, dobs, prob, iterations, mode="plain", seed=0, K=16, warmup=2, sur_
 
     Record fields: iteration, best, mean, median, evaluations (FD, cumulative),
     best_position (last record only: the global best's node values),
-    wall_s (cumulative, FD + host + surrogate), and in screened mode
+    wall_s (cumulative, FD + host + surrogate), fd_s (cumulative seconds in
+    the FD fitness, the result's copy to the host included), gpt_updates_per_s
+    (this iteration's FD point-updates over its FD seconds), evaluated_fraction
+    (the share of the swarm sent to the FD fitness), and in screened mode
     surrogate_rho (Spearman correlation between the surrogate's prediction and
     the FD misfit of the evaluated particles, measured before it trains on
     them) and surrogate_mae (mean absolute error of the standardised
@@ -141,9 +144,13 @@ def run(geom, dobs, prob, iterations, mode="plain", seed=0, K=16, warmup=2, sur_
     logf = open(log_path, "a") if log_path else None
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    fd_s = 0.0
     for it in range(iterations):
         x = swarm.ask()
+        t1 = time.perf_counter()
         f = fb(x).cpu().numpy().astype(np.float64)
+        t_fd = time.perf_counter() - t1
+        fd_s += t_fd
         rec_extra = {}
         if isinstance(sur, Surrogate) and swarm.k >= swarm.warmup:
             pred = sur.predict(x)
@@ -154,6 +161,9 @@ def run(geom, dobs, prob, iterations, mode="plain", seed=0, K=16, warmup=2, sur_
         rec = dict(swarm.tell(f))
         rec.update(rec_extra)
         rec["wall_s"] = time.perf_counter() - t0
+        rec["fd_s"] = fd_s
+        rec["gpt_updates_per_s"] = fb.updates / t_fd / 1e9
+        rec["evaluated_fraction"] = len(x) / N
         rec["mode"] = mode
         out.append(rec)
         if logf:
